@@ -1,0 +1,609 @@
+/* FP64 CPU oracle of the tight-frame (TF) cone-beam CT iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the GPU library.  It shares no
+ * source, header, table or helper with the GPU code.
+ *
+ * Paper: Jia, Dong, Lou & Jiang, "GPU-based Iterative Cone Beam CT
+ * Reconstruction Using Tight Frame Regularization", arXiv 1008.2042.
+ *
+ * What is computed, section by section of the paper:
+ *   section 2.1, Eq. (1)      the cone-beam line integral P (Joseph discretisation)
+ *   Appendix 2, Eq. (A1)      its adjoint P^T, here the exact matrix transpose
+ *   section 2.1 (filters)     the 27-band piecewise-linear tight frame W and W^T
+ *   section 2.1, Eq. (2)      the vector shrinkage T_mu, then positivity H
+ *   Appendix 1                CGLS warm-started from v
+ *   section 2.1, Alg. A1/A2   the outer iteration, A2 with the t-momentum
+ *   section 2.2.3             the coarse-to-fine multigrid schedule
+ *
+ * Readings where the paper is silent (each one is listed with its reason in
+ * the design notes of the repository):
+ *   - geometry: source at (SAD cos t, SAD sin t, 0); flat detector through
+ *     -(SDD-SAD)(cos t, sin t, 0) with axes e_u = (-sin t, cos t, 0),
+ *     e_v = (0, 0, 1); detector values are point samples at pixel centres
+ *     u_c = (c-(nu-1)/2) du, v_r = (r-(nv-1)/2) dv; voxel centres
+ *     x_i = (i-(nx-1)/2) dx (same for y, z).
+ *   - P: the paper traces rays with Siddon's method; the line integral of
+ *     Eq. (1) is discretised here by Joseph's method instead: one stepping
+ *     axis per view (x when |cos t| >= |sin t| - 1e-12, else y); on every
+ *     voxel-centre plane of that axis crossed at ray parameter 0 < tau < 1
+ *     the volume is interpolated bilinearly in the other two axes (zero
+ *     outside the grid), and the sum is scaled by the path length between
+ *     consecutive planes, l = d_step |a| / |a_step|.
+ *   - P^T: the exact transpose of that matrix (the paper's closed form
+ *     Eq. (3) is its continuous limit).
+ *   - W: convolution with half-sample symmetric extension of f; W^T is its
+ *     exact adjoint, so W^T W = I holds exactly.
+ *   - CGLS: cgls_steps counts q = P p products; the last P^T is skipped since
+ *     the output never uses it; guard 1e-300 on gamma and ||q||^2.
+ *   - multigrid: coarse grids halve every axis (ceil), double the voxel size
+ *     and stay centred; detector 2x2 binned (mean); prolongation is trilinear
+ *     with the coarse index clamped to the grid; A2 restarts (t = 1) per grid.
+ */
+#include "tf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Deterministic FP64 dot product: fixed chunks summed in index order.        */
+/* ------------------------------------------------------------------------- */
+#define DOT_CHUNK 4096
+static double dot(const double* a, const double* b, int64_t n) {
+  int64_t nchunk = (n + DOT_CHUNK - 1) / DOT_CHUNK;
+  if (nchunk == 0) return 0.0;
+  double* part = (double*)malloc(sizeof(double) * (size_t)nchunk);
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < nchunk; ++c) {
+    int64_t lo = c * DOT_CHUNK, hi = lo + DOT_CHUNK < n ? lo + DOT_CHUNK : n;
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; ++i) s += a[i] * b[i];
+    part[c] = s;
+  }
+  double s = 0.0;
+  for (int64_t c = 0; c < nchunk; ++c) s += part[c];
+  free(part);
+  return s;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Geometry (section 2.1, Eq. (1) and Fig. 1; conventions are this reading)  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int step_x;      /* 1: planes x = x_i; 0: planes y = y_j */
+  double cs, sn;   /* cos, sin of the view angle */
+  double sx, sy;   /* source position (z = 0) */
+} view_t;
+
+static double view_angle(const orc_geom* g, int k) {
+  return g->angles ? g->angles[k] : 2.0 * M_PI * (double)k / (double)g->n_views;
+}
+
+static view_t make_view(const orc_geom* g, int k) {
+  view_t v;
+  double t = view_angle(g, k);
+  v.cs = cos(t);
+  v.sn = sin(t);
+  v.sx = g->sad * v.cs;
+  v.sy = g->sad * v.sn;
+  v.step_x = fabs(v.cs) >= fabs(v.sn) - 1e-12;
+  return v;
+}
+
+static double hat(double t) {
+  double a = 1.0 - fabs(t);
+  return a > 0.0 ? a : 0.0;
+}
+
+/* The (at most four) voxel taps of ray (c, r) of view v on plane p of the
+ * view's stepping axis.  Weights include the path length l.  Returns the
+ * number of taps written to idx/w. */
+static int plane_taps(const orc_geom* g, const view_t* v, int c, int r, int p,
+                      int64_t idx[4], double w[4]) {
+  double uc = ((double)c - 0.5 * (g->nu - 1)) * g->du;
+  double vr = ((double)r - 0.5 * (g->nv - 1)) * g->dv;
+  double ax = -g->sdd * v->cs - uc * v->sn;
+  double ay = -g->sdd * v->sn + uc * v->cs;
+  double az = vr;
+  double alen = sqrt(ax * ax + ay * ay + az * az);
+  int nx = g->nx, ny = g->ny, nz = g->nz;
+  double th, zh, ell; /* transverse index, z index, path length */
+  if (v->step_x) {
+    double xp = ((double)p - 0.5 * (nx - 1)) * g->dx;
+    double tau = (xp - v->sx) / ax;
+    if (!(tau > 0.0 && tau < 1.0)) return 0;
+    double Y = v->sy + tau * ay, Z = tau * az;
+    th = Y / g->dy + 0.5 * (ny - 1);
+    zh = Z / g->dz + 0.5 * (nz - 1);
+    ell = g->dx * alen / fabs(ax);
+  } else {
+    double yp = ((double)p - 0.5 * (ny - 1)) * g->dy;
+    double tau = (yp - v->sy) / ay;
+    if (!(tau > 0.0 && tau < 1.0)) return 0;
+    double X = v->sx + tau * ax, Z = tau * az;
+    th = X / g->dx + 0.5 * (nx - 1);
+    zh = Z / g->dz + 0.5 * (nz - 1);
+    ell = g->dy * alen / fabs(ay);
+  }
+  int ntr = v->step_x ? ny : nx;
+  int t0 = (int)floor(th), z0 = (int)floor(zh);
+  int n = 0;
+  for (int kk = z0; kk <= z0 + 1; ++kk) {
+    if (kk < 0 || kk >= nz) continue;
+    for (int tt = t0; tt <= t0 + 1; ++tt) {
+      if (tt < 0 || tt >= ntr) continue;
+      double wt = hat(th - tt) * hat(zh - kk);
+      if (wt == 0.0) continue;
+      int i = v->step_x ? p : tt;
+      int j = v->step_x ? tt : p;
+      idx[n] = ((int64_t)kk * ny + j) * nx + i;
+      w[n] = ell * wt;
+      ++n;
+    }
+  }
+  return n;
+}
+
+static int n_planes(const orc_geom* g, const view_t* v) {
+  return v->step_x ? g->nx : g->ny;
+}
+
+static double ray_integral(const orc_geom* g, const view_t* v, int c, int r,
+                           const double* f) {
+  double s = 0.0;
+  int np = n_planes(g, v);
+  for (int p = 0; p < np; ++p) {
+    int64_t idx[4];
+    double w[4];
+    int n = plane_taps(g, v, c, r, p, idx, w);
+    for (int t = 0; t < n; ++t) s += w[t] * f[idx[t]];
+  }
+  return s;
+}
+
+void orc_project(const orc_geom* g, const double* f, double* proj) {
+  int nu = g->nu, nv = g->nv;
+  for (int k = 0; k < g->n_views; ++k) {
+    view_t v = make_view(g, k);
+    double* out = proj + (int64_t)k * nu * nv;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int r = 0; r < nv; ++r)
+      for (int c = 0; c < nu; ++c) out[(int64_t)r * nu + c] = ray_integral(g, &v, c, r, f);
+  }
+}
+
+void orc_project_rays(const orc_geom* g, const double* f, int64_t n,
+                      const int32_t* vrc, double* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < n; ++q) {
+    view_t v = make_view(g, vrc[3 * q]);
+    out[q] = ray_integral(g, &v, vrc[3 * q + 2], vrc[3 * q + 1], f);
+  }
+}
+
+/* Transpose by scatter: a thread owns one plane of the stepping axis and
+ * visits every ray of the view, so no two threads write the same voxel. */
+void orc_backproject(const orc_geom* g, const double* proj, double* f) {
+  int64_t nvox = (int64_t)g->nx * g->ny * g->nz;
+  memset(f, 0, sizeof(double) * (size_t)nvox);
+  int nu = g->nu, nv = g->nv;
+  for (int k = 0; k < g->n_views; ++k) {
+    view_t v = make_view(g, k);
+    const double* in = proj + (int64_t)k * nu * nv;
+    int np = n_planes(g, &v);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < np; ++p)
+      for (int r = 0; r < nv; ++r)
+        for (int c = 0; c < nu; ++c) {
+          int64_t idx[4];
+          double w[4];
+          int n = plane_taps(g, &v, c, r, p, idx, w);
+          double val = in[(int64_t)r * nu + c];
+          for (int t = 0; t < n; ++t) f[idx[t]] += w[t] * val;
+        }
+  }
+}
+
+void orc_backproject_voxels(const orc_geom* g, const double* proj, int64_t n,
+                            const int32_t* kji, double* out) {
+  int nu = g->nu, nv = g->nv;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < n; ++q) {
+    int k = kji[3 * q], j = kji[3 * q + 1], i = kji[3 * q + 2];
+    int64_t target = ((int64_t)k * g->ny + j) * g->nx + i;
+    double s = 0.0;
+    for (int vw = 0; vw < g->n_views; ++vw) {
+      view_t v = make_view(g, vw);
+      int p = v.step_x ? i : j;
+      const double* in = proj + (int64_t)vw * nu * nv;
+      for (int r = 0; r < nv; ++r)
+        for (int c = 0; c < nu; ++c) {
+          int64_t idx[4];
+          double w[4];
+          int m = plane_taps(g, &v, c, r, p, idx, w);
+          for (int t = 0; t < m; ++t)
+            if (idx[t] == target) s += w[t] * in[(int64_t)r * nu + c];
+        }
+    }
+    out[q] = s;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tight frame (section 2.1): h0 = [1,2,1]/4, h1 = sqrt(2)/4 [1,0,-1],        */
+/* h2 = [-1,2,-1]/4; band i = 9n + 3m + l is h_l(x) h_m(y) h_n(z).            */
+/* ------------------------------------------------------------------------- */
+
+/* Filter taps listed as h[-1], h[0], h[+1]. */
+static double filt(int l, int m) {
+  const double q = sqrt(2.0) / 4.0;
+  static const double h0[3] = {0.25, 0.5, 0.25};
+  static const double h2[3] = {-0.25, 0.5, -0.25};
+  if (l == 0) return h0[m + 1];
+  if (l == 2) return h2[m + 1];
+  return m == -1 ? q : (m == 1 ? -q : 0.0);
+}
+
+/* Half-sample symmetric reflection into [0, N). */
+static int reflect(int j, int N) {
+  while (j < 0 || j >= N) j = (j < 0) ? -1 - j : 2 * N - 1 - j;
+  return j;
+}
+
+/* One 1-D analysis operator A_l of length N with dilation d, as rows of
+ * three (column, value) entries: (A_l f)[n] = sum_m h_l[m] f[R(n - m d)]. */
+typedef struct {
+  int N;
+  int* col;    /* 3N */
+  double* val; /* 3N */
+} op1d;
+
+static op1d make_op(int N, int d, int l) {
+  op1d o;
+  o.N = N;
+  o.col = (int*)malloc(sizeof(int) * 3 * (size_t)N);
+  o.val = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+  for (int n = 0; n < N; ++n)
+    for (int m = -1; m <= 1; ++m) {
+      o.col[3 * n + m + 1] = reflect(n - m * d, N);
+      o.val[3 * n + m + 1] = filt(l, m);
+    }
+  return o;
+}
+static void free_op(op1d* o) {
+  free(o->col);
+  free(o->val);
+}
+
+/* out (+)= A in along one axis (axis 0 = x, 1 = y, 2 = z), or A^T in when
+ * transpose is set.  Lines along the axis are independent. */
+static void apply_axis(int nx, int ny, int nz, int axis, const op1d* A,
+                       int transpose, const double* in, double* out, int accumulate) {
+  int64_t nvox = (int64_t)nx * ny * nz;
+  if (!accumulate) memset(out, 0, sizeof(double) * (size_t)nvox);
+  int N = axis == 0 ? nx : (axis == 1 ? ny : nz);
+  int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx : (int64_t)nx * ny);
+  int64_t nlines = nvox / N;
+#pragma omp parallel for schedule(static)
+  for (int64_t L = 0; L < nlines; ++L) {
+    int64_t base;
+    if (axis == 0) base = L * nx;
+    else if (axis == 1) base = (L / nx) * (int64_t)nx * ny + (L % nx);
+    else base = L;
+    for (int n = 0; n < N; ++n)
+      for (int e = 0; e < 3; ++e) {
+        int col = A->col[3 * n + e];
+        double v = A->val[3 * n + e];
+        if (!transpose) out[base + n * stride] += v * in[base + col * stride];
+        else out[base + col * stride] += v * in[base + n * stride];
+      }
+  }
+}
+
+void orc_framelet_analysis(int32_t nx, int32_t ny, int32_t nz, int32_t dil,
+                           const double* f, double* coeff) {
+  int64_t V = (int64_t)nx * ny * nz;
+  double* tx = (double*)malloc(sizeof(double) * (size_t)V);
+  double* txy = (double*)malloc(sizeof(double) * (size_t)V);
+  for (int l = 0; l < 3; ++l) {
+    op1d Ax = make_op(nx, dil, l);
+    apply_axis(nx, ny, nz, 0, &Ax, 0, f, tx, 0);
+    for (int m = 0; m < 3; ++m) {
+      op1d Ay = make_op(ny, dil, m);
+      apply_axis(nx, ny, nz, 1, &Ay, 0, tx, txy, 0);
+      for (int n = 0; n < 3; ++n) {
+        op1d Az = make_op(nz, dil, n);
+        apply_axis(nx, ny, nz, 2, &Az, 0, txy, coeff + (int64_t)(9 * n + 3 * m + l) * V, 0);
+        free_op(&Az);
+      }
+      free_op(&Ay);
+    }
+    free_op(&Ax);
+  }
+  free(tx);
+  free(txy);
+}
+
+void orc_framelet_synthesis(int32_t nx, int32_t ny, int32_t nz, int32_t dil,
+                            const double* coeff, double* f) {
+  int64_t V = (int64_t)nx * ny * nz;
+  double* az = (double*)malloc(sizeof(double) * (size_t)V);
+  double* ayz = (double*)malloc(sizeof(double) * (size_t)V);
+  memset(f, 0, sizeof(double) * (size_t)V);
+  for (int l = 0; l < 3; ++l) {
+    memset(ayz, 0, sizeof(double) * (size_t)V);
+    for (int m = 0; m < 3; ++m) {
+      memset(az, 0, sizeof(double) * (size_t)V);
+      for (int n = 0; n < 3; ++n) {
+        op1d Az = make_op(nz, dil, n);
+        apply_axis(nx, ny, nz, 2, &Az, 1, coeff + (int64_t)(9 * n + 3 * m + l) * V, az, 1);
+        free_op(&Az);
+      }
+      op1d Ay = make_op(ny, dil, m);
+      apply_axis(nx, ny, nz, 1, &Ay, 1, az, ayz, 1);
+      free_op(&Ay);
+    }
+    op1d Ax = make_op(nx, dil, l);
+    apply_axis(nx, ny, nz, 0, &Ax, 1, ayz, f, 1);
+    free_op(&Ax);
+  }
+  free(az);
+  free(ayz);
+}
+
+/* Eq. (2): the low band is kept; the 26 high bands at a voxel are scaled by
+ * max(1 - mu / ||alpha_h||, 0), taken as 0 when ||alpha_h|| <= mu. */
+void orc_shrink(int64_t nvox, double lambda, double* coeff) {
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < nvox; ++x) {
+    double n2 = 0.0;
+    for (int b = 1; b < 27; ++b) n2 += coeff[b * nvox + x] * coeff[b * nvox + x];
+    double nrm = sqrt(n2);
+    double s = nrm <= lambda ? 0.0 : 1.0 - lambda / nrm;
+    for (int b = 1; b < 27; ++b) coeff[b * nvox + x] *= s;
+  }
+}
+
+void orc_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t levels,
+                         double lambda, int32_t positivity, const double* in,
+                         double* out) {
+  int64_t V = (int64_t)nx * ny * nz;
+  double* c1 = (double*)malloc(sizeof(double) * 27 * (size_t)V);
+  orc_framelet_analysis(nx, ny, nz, 1, in, c1);
+  if (levels >= 2) {
+    /* Second level: the dilated (taps -2, 0, +2) frame applied to the level-1
+     * low band; each level is shrunk on its own 26 high bands. */
+    double* c2 = (double*)malloc(sizeof(double) * 27 * (size_t)V);
+    orc_framelet_analysis(nx, ny, nz, 2, c1, c2);
+    orc_shrink(V, lambda, c2);
+    orc_framelet_synthesis(nx, ny, nz, 2, c2, c1);
+    free(c2);
+  }
+  orc_shrink(V, lambda, c1);
+  orc_framelet_synthesis(nx, ny, nz, 1, c1, out);
+  free(c1);
+  if (positivity)
+    for (int64_t x = 0; x < V; ++x)
+      if (out[x] < 0.0) out[x] = 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* CGLS (Appendix 1)                                                         */
+/* ------------------------------------------------------------------------- */
+int orc_cgls(const orc_geom* g, double* x, const double* proj, int32_t n,
+             double* resid2, double* resid_hist) {
+  int64_t V = (int64_t)g->nx * g->ny * g->nz;
+  int64_t S = (int64_t)g->n_views * g->nu * g->nv;
+  double* r = (double*)malloc(sizeof(double) * (size_t)S);
+  double* q = (double*)malloc(sizeof(double) * (size_t)S);
+  double* s = (double*)malloc(sizeof(double) * (size_t)V);
+  double* p = (double*)malloc(sizeof(double) * (size_t)V);
+  const double tiny = 1e-300;
+  int broke = 0;
+
+  orc_project(g, x, r);
+  for (int64_t i = 0; i < S; ++i) r[i] = proj[i] - r[i];
+  if (resid_hist) {
+    for (int l = 0; l <= n; ++l) resid_hist[l] = NAN;
+    resid_hist[0] = dot(r, r, S);
+  }
+  orc_backproject(g, r, s);
+  memcpy(p, s, sizeof(double) * (size_t)V);
+  double gamma = dot(s, s, V);
+
+  for (int l = 0; l < n; ++l) {
+    orc_project(g, p, q);
+    double delta = dot(q, q, S);
+    if (gamma <= tiny || delta <= tiny) {
+      broke = 1;
+      break;
+    }
+    double alpha = gamma / delta;
+    for (int64_t i = 0; i < V; ++i) x[i] += alpha * p[i];
+    for (int64_t i = 0; i < S; ++i) r[i] -= alpha * q[i];
+    if (resid_hist) resid_hist[l + 1] = dot(r, r, S);
+    if (l < n - 1) {
+      orc_backproject(g, r, s);
+      double gnew = dot(s, s, V);
+      double beta = gnew / gamma;
+      for (int64_t i = 0; i < V; ++i) p[i] = s[i] + beta * p[i];
+      gamma = gnew;
+    }
+  }
+  if (resid2) *resid2 = dot(r, r, S);
+  free(r);
+  free(q);
+  free(s);
+  free(p);
+  return broke;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multigrid transfer (section 2.2.3)                                         */
+/* ------------------------------------------------------------------------- */
+void orc_coarse_geom(const orc_geom* fine, int32_t bin_detector, orc_geom* c) {
+  *c = *fine;
+  c->nx = (fine->nx + 1) / 2;
+  c->ny = (fine->ny + 1) / 2;
+  c->nz = (fine->nz + 1) / 2;
+  c->dx = 2.0 * fine->dx;
+  c->dy = 2.0 * fine->dy;
+  c->dz = 2.0 * fine->dz;
+  if (bin_detector) {
+    c->nu = (fine->nu + 1) / 2;
+    c->nv = (fine->nv + 1) / 2;
+    c->du = 2.0 * fine->du;
+    c->dv = 2.0 * fine->dv;
+  }
+}
+
+/* Coarse pixel (r, c) is the mean of the fine pixels {2r, 2r+1} x {2c, 2c+1}
+ * that exist. */
+void orc_restrict_sino(const orc_geom* fine, const double* in, double* out) {
+  int nu = fine->nu, nv = fine->nv, nuc = (nu + 1) / 2, nvc = (nv + 1) / 2;
+  for (int k = 0; k < fine->n_views; ++k) {
+    const double* a = in + (int64_t)k * nu * nv;
+    double* b = out + (int64_t)k * nuc * nvc;
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < nvc; ++r)
+      for (int c = 0; c < nuc; ++c) {
+        double s = 0.0;
+        int cnt = 0;
+        for (int dr = 0; dr < 2; ++dr)
+          for (int dc = 0; dc < 2; ++dc) {
+            int rr = 2 * r + dr, cc = 2 * c + dc;
+            if (rr < nv && cc < nu) {
+              s += a[(int64_t)rr * nu + cc];
+              ++cnt;
+            }
+          }
+        b[(int64_t)r * nuc + c] = s / cnt;
+      }
+  }
+}
+
+/* Linear interpolation of the coarse solution at each fine voxel centre, the
+ * coarse fractional index clamped to the coarse grid on every axis. */
+static void lin_index(double pos, double dc, int nc, int* i0, int* i1, double* w1) {
+  double t = pos / dc + 0.5 * (nc - 1);
+  if (t < 0.0) t = 0.0;
+  if (t > nc - 1) t = nc - 1;
+  int a = (int)floor(t);
+  if (a > nc - 1) a = nc - 1;
+  *i0 = a;
+  *i1 = a + 1 < nc ? a + 1 : nc - 1;
+  *w1 = t - a;
+}
+
+void orc_prolong_vol(const orc_geom* co, const orc_geom* fi, const double* in,
+                     double* out) {
+  int nx = fi->nx, ny = fi->ny, nz = fi->nz;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        int x0, x1, y0, y1, z0, z1;
+        double wx, wy, wz;
+        lin_index((i - 0.5 * (nx - 1)) * fi->dx, co->dx, co->nx, &x0, &x1, &wx);
+        lin_index((j - 0.5 * (ny - 1)) * fi->dy, co->dy, co->ny, &y0, &y1, &wy);
+        lin_index((k - 0.5 * (nz - 1)) * fi->dz, co->dz, co->nz, &z0, &z1, &wz);
+        int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+        double wxs[2] = {1 - wx, wx}, wys[2] = {1 - wy, wy}, wzs[2] = {1 - wz, wz};
+        double s = 0.0;
+        for (int c = 0; c < 2; ++c)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a)
+              s += wzs[c] * wys[b] * wxs[a] *
+                   in[((int64_t)zs[c] * co->ny + ys[b]) * co->nx + xs[a]];
+        out[((int64_t)k * ny + j) * nx + i] = s;
+      }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm A2 (A1 with momentum = 0) and the multigrid driver               */
+/* ------------------------------------------------------------------------- */
+int orc_tf_iterations(const orc_geom* g, const orc_opts* o, const double* proj,
+                      int32_t n_iters, double* vol, orc_report* rep) {
+  int64_t V = (int64_t)g->nx * g->ny * g->nz;
+  double* f_prev = (double*)malloc(sizeof(double) * (size_t)V);
+  double* f_cur = (double*)malloc(sizeof(double) * (size_t)V);
+  double* x = (double*)malloc(sizeof(double) * (size_t)V);
+  memcpy(f_cur, vol, sizeof(double) * (size_t)V);
+  memcpy(f_prev, vol, sizeof(double) * (size_t)V);
+  double t_prev = 1.0, t_cur = 1.0;
+  for (int k = 0; k < n_iters; ++k) {
+    double c = o->momentum ? (t_prev - 1.0) / t_cur : 0.0;
+    for (int64_t i = 0; i < V; ++i) x[i] = f_cur[i] + c * (f_cur[i] - f_prev[i]);
+    double r2 = 0.0;
+    int broke = orc_cgls(g, x, proj, o->cgls_steps, &r2, NULL);
+    if (rep) {
+      rep->cgls_breakdowns += broke;
+      rep->resid2_last = r2;
+    }
+    double* tmp = f_prev;
+    f_prev = f_cur;
+    f_cur = tmp;
+    orc_framelet_shrink(g->nx, g->ny, g->nz, o->framelet_levels, o->lambda,
+                        o->positivity, x, f_cur);
+    double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t_cur * t_cur));
+    t_prev = t_cur;
+    t_cur = t_next;
+  }
+  memcpy(vol, f_cur, sizeof(double) * (size_t)V);
+  free(f_prev);
+  free(f_cur);
+  free(x);
+  return 0;
+}
+
+int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
+                    double* vol, orc_report* rep) {
+  int ng = o->n_grids;
+  if (ng < 1 || ng > 4) return -1;
+  orc_geom geo[4];
+  double* sino[4];
+  geo[0] = *g;
+  sino[0] = (double*)proj;
+  for (int l = 1; l < ng; ++l) {
+    orc_coarse_geom(&geo[l - 1], o->bin_coarse_detector, &geo[l]);
+    int64_t S = (int64_t)geo[l].n_views * geo[l].nu * geo[l].nv;
+    sino[l] = (double*)malloc(sizeof(double) * (size_t)S);
+    if (o->bin_coarse_detector) orc_restrict_sino(&geo[l - 1], sino[l - 1], sino[l]);
+    else memcpy(sino[l], sino[l - 1], sizeof(double) * (size_t)S);
+  }
+  if (rep) memset(rep, 0, sizeof(*rep));
+  double* cur = NULL;
+  for (int l = ng - 1; l >= 0; --l) {
+    int64_t V = (int64_t)geo[l].nx * geo[l].ny * geo[l].nz;
+    double* f = (double*)malloc(sizeof(double) * (size_t)V);
+    if (cur == NULL) memset(f, 0, sizeof(double) * (size_t)V);
+    else {
+      orc_prolong_vol(&geo[l + 1], &geo[l], cur, f);
+      free(cur);
+    }
+    int it = o->iters[ng - 1 - l];
+    orc_tf_iterations(&geo[l], o, sino[l], it, f, rep);
+    if (rep) rep->iters_done[ng - 1 - l] = it;
+    cur = f;
+  }
+  memcpy(vol, cur, sizeof(double) * (size_t)g->nx * g->ny * g->nz);
+  free(cur);
+  for (int l = 1; l < ng; ++l) free(sino[l]);
+  return 0;
+}

@@ -1,0 +1,97 @@
+/* FP64 CPU oracle of the tight-frame (TF) cone-beam CT iteration of
+ * Jia, Dong, Lou & Jiang, "GPU-based Iterative Cone Beam CT Reconstruction
+ * Using Tight Frame Regularization" (arXiv 1008.2042).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The GPU library
+ * never includes, links or calls anything here, and nothing here is shared
+ * with it.
+ *
+ * Everything is IEEE double precision, plain loops, OpenMP only across
+ * independent outputs (every result is deterministic).
+ *
+ * Conventions (the paper leaves them open; see the geometry comment in
+ * tf_oracle.c):
+ *   volume    f[k][j][i], i along x (fastest), voxel centres
+ *             x_i = (i - (nx-1)/2) dx, same for y, z
+ *   sinogram  g[view][r][c], c along the detector u axis (fastest)
+ *   view k    theta_k = angles[k], or 2 pi k / n_views when angles is NULL
+ */
+#ifndef TF_ORACLE_H
+#define TF_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx, dy, dz;
+  int32_t nu, nv;
+  double du, dv;
+  double sad, sdd;
+  int32_t n_views;
+  const double* angles; /* NULL => equally spaced over 360 degrees */
+} orc_geom;
+
+typedef struct {
+  double lambda;        /* shrink threshold (the paper's mu) */
+  int32_t n_grids;      /* multigrid levels, 1..4 */
+  int32_t iters[4];     /* outer iterations per grid, coarsest first */
+  int32_t cgls_steps;   /* q = P p steps per CGLS call */
+  int32_t framelet_levels; /* 1 or 2 */
+  int32_t momentum;     /* 1 = Algorithm A2, 0 = Algorithm A1 */
+  int32_t positivity;   /* 1 = apply H */
+  int32_t bin_coarse_detector; /* 1 = 2x2 detector binning on coarser grids */
+} orc_opts;
+
+typedef struct {
+  double resid2_last;      /* ||g - P x||^2 after the last CGLS update */
+  int32_t cgls_breakdowns; /* CGLS calls stopped by the 1e-300 guard */
+  int32_t iters_done[4];
+} orc_report;
+
+int orc_num_threads(void);
+
+/* Cone-beam projection, Eq. (1) discretised by Joseph's method. */
+void orc_project(const orc_geom* g, const double* f, double* proj);
+/* The same, for a list of n rays (view, row, col) only. */
+void orc_project_rays(const orc_geom* g, const double* f, int64_t n,
+                      const int32_t* vrc, double* out);
+/* Exact matrix transpose of orc_project (scatter form). */
+void orc_backproject(const orc_geom* g, const double* proj, double* f);
+/* The transpose evaluated at n voxels (k, j, i) only (gather over all rays). */
+void orc_backproject_voxels(const orc_geom* g, const double* proj, int64_t n,
+                            const int32_t* kji, double* out);
+
+/* Framelet analysis W of one level: coeff[27][nz][ny][nx], band 9n+3m+l. */
+void orc_framelet_analysis(int32_t nx, int32_t ny, int32_t nz, int32_t dil,
+                           const double* f, double* coeff);
+/* Exact adjoint W^T of orc_framelet_analysis. */
+void orc_framelet_synthesis(int32_t nx, int32_t ny, int32_t nz, int32_t dil,
+                            const double* coeff, double* f);
+/* Vector shrink of Eq. (2), in place on coeff[27][V]. */
+void orc_shrink(int64_t nvox, double lambda, double* coeff);
+/* f_out = H(W^T T_lambda W f_in) with 1 or 2 framelet levels. */
+void orc_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t levels,
+                         double lambda, int32_t positivity, const double* in,
+                         double* out);
+
+/* n CGLS steps (Appendix 1) warm-started from x (updated in place).
+ * Returns 1 when the breakdown guard stopped the call.  resid2 (nullable)
+ * receives ||g - P x||^2 at exit; resid_hist (nullable, n+1 entries) the
+ * residual norm^2 after init and after each step. */
+int orc_cgls(const orc_geom* g, double* x, const double* proj, int32_t n,
+             double* resid2, double* resid_hist);
+
+/* Multigrid transfer operators (section 2.2.3). */
+void orc_coarse_geom(const orc_geom* fine, int32_t bin_detector, orc_geom* coarse);
+void orc_restrict_sino(const orc_geom* fine, const double* in, double* out);
+void orc_prolong_vol(const orc_geom* coarse, const orc_geom* fine,
+                     const double* in, double* out);
+
+/* Full reconstruction: Algorithm A2 (or A1) inside the coarse-to-fine schedule. */
+int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
+                    double* vol, orc_report* rep);
+/* n_iters outer iterations on one grid, starting from f_cur = f_prev = vol. */
+int orc_tf_iterations(const orc_geom* g, const orc_opts* o, const double* proj,
+                      int32_t n_iters, double* vol, orc_report* rep);
+
+#endif

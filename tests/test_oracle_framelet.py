@@ -1,0 +1,171 @@
+"""Pins of the oracle's tight frame W / W^T (section 2.1 filters) and the
+vector shrinkage of Eq. (2) with positivity H."""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from brute import analysis_scipy, framelet_matrix, kernel3d, shrink_dense
+from paper_1008_2042_amd.inputs import random_field
+
+_SCALE = {"1/4": 0.25, "sqrt(2)/4": math.sqrt(2.0) / 4.0}
+SHAPES = [(5, 4, 3), (4, 6, 7), (1, 2, 3), (2, 1, 1), (1, 1, 1), (3, 3, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("dil", [1, 2])
+def test_analysis_matches_scipy_reflect_convolution(shape, dil):
+    if dil == 2 and min(shape) < 2:
+        pytest.skip("scipy's reflect mode needs N >= 2 for taps +-2")
+    f = random_field(shape, 11)
+    got = oracle.framelet_analysis(f, dil)
+    want = analysis_scipy(f, dil)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("dil", [1, 2])
+def test_tight_frame_identity(shape, dil):
+    """W^T W = I and ||W f|| = ||f|| (the tight-frame property)."""
+    f = random_field(shape, 12)
+    c = oracle.framelet_analysis(f, dil)
+    back = oracle.framelet_synthesis(c, dil)
+    np.testing.assert_allclose(back, f, rtol=0, atol=1e-14)
+    assert abs(np.linalg.norm(c) - np.linalg.norm(f)) <= 1e-13 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("shape,dil", [((3, 4, 5), 1), ((3, 4, 5), 2), ((1, 2, 3), 1)])
+def test_synthesis_is_matrix_transpose(shape, dil):
+    W = framelet_matrix(shape, dil)
+    n = int(np.prod(shape))
+    WT = np.zeros((n, 27 * n))
+    for j in range(27 * n):
+        e = np.zeros(27 * n)
+        e[j] = 1.0
+        WT[:, j] = oracle.framelet_synthesis(e.reshape((27,) + shape), dil).ravel()
+    np.testing.assert_allclose(WT, W.T, rtol=0, atol=1e-15)
+
+
+def test_constant_and_ramp():
+    f = np.full((6, 7, 8), 0.37)
+    c = oracle.framelet_analysis(f)
+    np.testing.assert_allclose(c[0], 0.37, atol=1e-15)
+    np.testing.assert_allclose(c[1:], 0.0, atol=1e-15)
+    # linear ramp along x: every band with the h2 (second difference) filter
+    # along x vanishes away from the reflected edges
+    x = np.arange(8, dtype=np.float64)
+    ramp = np.broadcast_to(0.5 + 0.1 * x, (6, 7, 8)).copy()
+    c = oracle.framelet_analysis(ramp)
+    for n in range(3):
+        for m in range(3):
+            np.testing.assert_allclose(c[9 * n + 3 * m + 2][:, :, 1:-1], 0.0, atol=1e-15)
+
+
+def test_lowpass_only_synthesis_is_double_smoothing():
+    """With only band 0 kept, W^T keeps A0^T A0 f; A0 is symmetric with a
+    symmetric filter, so this is two reflect-mode smoothings with h0^3."""
+    f = random_field((5, 6, 7), 13)
+    c = oracle.framelet_analysis(f)
+    c[1:] = 0.0
+    got = oracle.framelet_synthesis(c)
+    k = kernel3d(0, 0, 0)
+    want = ndi.convolve(ndi.convolve(f, k, mode="reflect"), k, mode="reflect")
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+
+
+def _coeff_with_norm(norm, lam_shape=(1, 1, 1), seed=0):
+    rng = np.random.default_rng(seed)
+    c = rng.normal(size=(27,) + lam_shape)
+    c[1:] *= norm / np.sqrt((c[1:] ** 2).sum(axis=0))
+    return c
+
+
+def test_shrink_hand_cases():
+    lam = 0.5
+    # norm below lambda -> all high bands zero, low band untouched
+    c = _coeff_with_norm(0.3)
+    s = oracle.shrink(c, lam)
+    assert np.all(s[1:] == 0.0) and s[0, 0, 0, 0] == c[0, 0, 0, 0]
+    # norm exactly lambda -> zero
+    c = np.zeros((27, 1, 1, 1))
+    c[5] = 0.5
+    s = oracle.shrink(c, lam)
+    assert np.all(s[1:] == 0.0)
+    # norm zero -> zero, no NaN
+    c = np.zeros((27, 1, 1, 1))
+    c[0] = 2.0
+    s = oracle.shrink(c, lam)
+    assert np.all(np.isfinite(s)) and s[0, 0, 0, 0] == 2.0 and np.all(s[1:] == 0.0)
+    # norm 2 lambda -> halved
+    c = np.zeros((27, 1, 1, 1))
+    c[3] = 0.6
+    c[20] = 0.8
+    s = oracle.shrink(c, lam)
+    assert s[3, 0, 0, 0] == pytest.approx(0.3, abs=1e-16)
+    assert s[20, 0, 0, 0] == pytest.approx(0.4, abs=1e-16)
+
+
+def test_shrink_field_matches_dense():
+    c = random_field((27, 4, 5, 6), 14)
+    for lam in (0.0, 0.5, 2.5, 10.0):
+        np.testing.assert_allclose(oracle.shrink(c, lam), shrink_dense(c, lam), rtol=0, atol=1e-15)
+
+
+def test_framelet_shrink_composition():
+    f = random_field((6, 7, 9), 15)
+    # lambda = 0, no H: identity (tight frame)
+    np.testing.assert_allclose(oracle.framelet_shrink(f, 0.0, 1, False), f, atol=1e-14)
+    np.testing.assert_allclose(oracle.framelet_shrink(f, 0.0, 2, False), f, atol=1e-14)
+    # lambda > 0: explicit matrices
+    W = framelet_matrix(f.shape)
+    lam = 0.2
+    c = (W @ f.ravel()).reshape((27,) + f.shape)
+    want = W.T @ shrink_dense(c, lam).ravel()
+    got = oracle.framelet_shrink(f, lam, 1, False)
+    np.testing.assert_allclose(got.ravel(), want, atol=1e-14)
+    gotH = oracle.framelet_shrink(f, lam, 1, True)
+    np.testing.assert_allclose(gotH.ravel(), np.maximum(want, 0.0), atol=1e-14)
+    # H is idempotent and leaves no negative voxel
+    assert gotH.min() >= 0.0
+
+
+def test_two_level_explicit():
+    f = random_field((4, 5, 6), 16)
+    lam = 0.15
+    W1 = framelet_matrix(f.shape, 1)
+    W2 = framelet_matrix(f.shape, 2)
+    n = f.size
+    c1 = (W1 @ f.ravel()).reshape((27,) + f.shape)
+    c2 = (W2 @ c1[0].ravel()).reshape((27,) + f.shape)
+    c2 = shrink_dense(c2, lam)
+    c1 = shrink_dense(c1, lam)
+    c1[0] = (W2.T @ c2.ravel()).reshape(f.shape)
+    want = W1.T @ c1.ravel()
+    got = oracle.framelet_shrink(f, lam, 2, False)
+    np.testing.assert_allclose(got.ravel(), want, atol=1e-14)
+    assert n == f.size
+
+
+def test_filters_match_paper_constants():
+    """The three 1-D filters printed in section 2.1 and their partition of unity
+    sum_l |h_l(w)|^2 = 1, from the golden fixture."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")) as fh:
+        gold = json.load(fh)
+    h = gold["framelet_filters"]
+    f = np.zeros((1, 1, 7))
+    f[0, 0, 3] = 1.0  # impulse: band (l, 0, 0) along x reproduces h_l (with h0 = 1 at N = 1 in y, z)
+    c = oracle.framelet_analysis(f)
+    for l, name in enumerate(["h0", "h1", "h2"]):
+        taps = np.array(h[name]["taps"], dtype=np.float64) * _SCALE[h[name]["scale"]]
+        # along y and z the single sample reflects onto itself: h0 sums to 1
+        got = c[l, 0, 0, 2:5]
+        np.testing.assert_allclose(got, taps, atol=1e-15)
+    w = np.linspace(0, math.pi, 17)
+    s = sum(np.abs(sum(t * np.exp(-1j * w * m) for t, m in zip(
+        np.array(h[n]["taps"]) * _SCALE[h[n]["scale"]], (-1, 0, 1)))) ** 2
+        for n in ("h0", "h1", "h2"))
+    np.testing.assert_allclose(s, 1.0, atol=1e-15)
