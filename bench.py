@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the TF-regularised CBCT reconstruction on one MI355X.
+
+One step = one full reconstruction of the paper-scale workload through the
+C-ABI: 512x512x70 volume (0.5 x 0.5 x 2.5 mm), 40 views over 360 degrees,
+512x384 flat detector (0.776 mm), SAD 1000 / SDD 1500 mm, a 20-ellipsoid
+seeded phantom with Poisson noise (I0 = 1e5), 2-grid multigrid with 16 + 24
+outer iterations of Algorithm A2, 3 CGLS steps each, 1-level framelet,
+lambda = 5e-4 /mm.  Projections are resident in HBM before timing starts;
+the volume is written to HBM.
+
+Prints ONE JSON line (rank 0) with the metric, the roofline of the dominant
+kernel (event-timed live in the timed steps on the launching stream) and
+the FP64 oracle's CPU baseline on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TF iterations/s + s/recon at 512²×70 (FP32 vs FP16-store); serving p99 latency"
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X: 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
+FLOPS_PER_SAMPLE = 16.0          # algorithmic work of one (ray, plane) sample
+KERNEL_NAMES = ["P (k_project)", "P^T (k_backproject)", "framelet (k_framelet)"]
+KERNEL_SOURCES = ["project.hip", "backproject.hip", "framelet.hip"]
+
+
+def plane_samples(g) -> int:
+    """Number of (ray, plane) samples of the Joseph projector with at least
+    one tap inside the grid: per ray, the planes p of its stepping axis with
+    0 < tau_p < 1, trans index in (-1, N_trans) and z index in (-1, N_z).
+    This is the unit count of one P (and one P^T) application."""
+    import numpy as np
+    th = g.view_angles()
+    cs, sn = np.cos(th), np.sin(th)
+    step_x = np.abs(cs) >= np.abs(sn) - 1e-12
+    u = (np.arange(g.nu) - 0.5 * (g.nu - 1)) * g.du
+    vz = ((np.arange(g.nv) - 0.5 * (g.nv - 1)) * g.dv / g.dz)[None, :]
+
+    def window(c0, c1, lo, hi, plo, phi):
+        # p with lo < c0 + c1 p < hi (c1 != 0), intersected with (plo, phi)
+        a, b = (lo - c0) / c1, (hi - c0) / c1
+        return np.maximum(plo, np.minimum(a, b)), np.minimum(phi, np.maximum(a, b))
+
+    total = 0
+    for k in range(g.n_views):
+        ax = -g.sdd * cs[k] - u * sn[k]
+        ay = -g.sdd * sn[k] + u * cs[k]
+        sx, sy = g.sad * cs[k], g.sad * sn[k]
+        if step_x[k]:
+            a_s, a_t, s_s, s_t, ns, nt, ds, dtr = ax, ay, sx, sy, g.nx, g.ny, g.dx, g.dy
+        else:
+            a_s, a_t, s_s, s_t, ns, nt, ds, dtr = ay, ax, sy, sx, g.ny, g.nx, g.dy, g.dx
+        tau0 = (-0.5 * (ns - 1) * ds - s_s) / a_s                     # per column
+        dtau = ds / a_s
+        t0 = (s_t + tau0 * a_t) / dtr + 0.5 * (nt - 1)
+        dt = dtau * a_t / dtr
+        lo, hi = window(tau0, dtau, 0.0, 1.0, -1.0, float(ns))
+        lo, hi = window(t0, dt, -1.0, float(nt), lo, hi)
+        zc = 0.5 * (g.nz - 1)
+        lo2, hi2 = window(tau0[:, None] * vz + zc, np.where(vz == 0, 1e-300, dtau[:, None] * vz),
+                          -1.0, float(g.nz), lo[:, None], hi[:, None])
+        n = np.ceil(hi2) - np.floor(lo2) - 1.0
+        total += int(np.sum(np.maximum(n, 0.0)))
+    return total
+
+
+def source_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1008_2042_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_idx: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current source of that kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    ent = t.get(KERNEL_SOURCES[kernel_idx])
+    if not ent or ent.get("source_hash") != source_hash([KERNEL_SOURCES[kernel_idx]]):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, y):
+    """The FP64 oracle on a bounded sample of the same workload: one outer
+    TF iteration (3 CGLS steps + framelet shrink) on the workload's coarse
+    grid (256x256x35 volume, 40 views of 256x192 binned data), timed on this
+    host's cores.  The full schedule's rate is extrapolated with the
+    fine/coarse work ratio 8 (rays x4, planes x2, voxels x8)."""
+    import numpy as np
+    import oracle
+    g = cfg["geom"]
+    gc = oracle.coarse_geom(g, True)
+    yc = oracle.restrict_sino(g, y)
+    f0 = np.zeros((gc.nz, gc.ny, gc.nx))
+    t0 = time.perf_counter()
+    oracle.tf_iterations(gc, yc, f0, 1, cfg["lam"], cfg["cgls_steps"])
+    t_c = time.perf_counter() - t0
+    n_c, n_f = cfg["iters"]
+    recon_s = (n_c + 8.0 * n_f) * t_c
+    return {"value": round((n_c + n_f) / recon_s, 6), "unit": "TF iterations/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "1 outer TF iteration (3 CGLS steps + framelet shrink) of the coarse "
+                      "256x256x35 grid of this workload took %.2f s; full 16+24 schedule "
+                      "extrapolated as (16 + 8*24) x that = %.0f s per reconstruction"
+                      % (t_c, recon_s)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f16", action="store_true", help="skip the FP16-storage companion run")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the reconstruction runs on a single MI355X; "
+              "multi-GPU sharding is a design note, not a measured path (got --gpus %d, "
+              "WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1008_2042_amd import inputs, tfcb
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    tfcb.load()
+    cfg = inputs.config("paper")
+    g = cfg["geom"]
+    y = inputs.measured_data(cfg)
+    yd = torch.tensor(y, dtype=torch.float32, device=dev)
+    n_iters = sum(cfg["iters"])
+
+    def run(storage, steps, warmup, profile):
+        opts = tfcb.options(cfg["lam"], cfg["iters"], cfg["cgls_steps"], cfg["framelet_levels"],
+                            storage=storage, profile=profile)
+        ws = torch.empty(tfcb.workspace_size(g, opts), dtype=torch.uint8, device=dev)
+        out = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)
+        kw = dict(cgls_steps=cfg["cgls_steps"], framelet_levels=cfg["framelet_levels"],
+                  storage=storage, out=out, ws=ws)
+        for _ in range(warmup):
+            tfcb.reconstruct(g, yd, cfg["lam"], cfg["iters"], **kw)
+        reps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, rep = tfcb.reconstruct(g, yd, cfg["lam"], cfg["iters"], profile=profile, **kw)
+            reps.append(rep)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return out.clone(), dt, reps
+
+    vol32, dt32, reps = run(tfcb.F32, args.steps, args.warmup, True)
+    ms_per_step = dt32 / args.steps * 1e3
+    value = n_iters * args.steps / dt32
+
+    # per-kernel averages over the timed steps (finest grid launches)
+    kms = np.sum([r["kernel_ms"] for r in reps], axis=0)
+    kn = np.sum([r["kernel_launches"] for r in reps], axis=0)
+    avg_ms = [float(kms[i] / kn[i]) if kn[i] else 0.0 for i in range(3)]
+    dom = int(np.argmax(kms[:3]))
+    samples = plane_samples(g)
+    roofline = None
+    if dom in (0, 1):
+        flops = samples * FLOPS_PER_SAMPLE
+        achieved = flops / (avg_ms[dom] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                    "traffic": load_traffic(dom), "kernel": KERNEL_NAMES[dom],
+                    "avg_launch_ms": round(avg_ms[dom], 4),
+                    "units_per_launch": samples, "flops_per_unit": FLOPS_PER_SAMPLE}
+    else:
+        nbytes = g.nx * g.ny * g.nz * 16.0
+        achieved = nbytes / (avg_ms[dom] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
+                    "traffic": load_traffic(dom), "kernel": KERNEL_NAMES[dom],
+                    "avg_launch_ms": round(avg_ms[dom], 4)}
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TF iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper-scale TF reconstruction: 512x512x70 volume at "
+                               "0.5x0.5x2.5 mm, 40 views, 512x384 detector at 0.776 mm, "
+                               "2-grid multigrid 16+24 iterations, 3 CGLS steps, 1-level "
+                               "framelet, lambda 5e-4, 20-ellipsoid phantom, Poisson I0=1e5",
+                   "s_per_recon": round(ms_per_step / 1e3, 4),
+                   "iterations_per_recon": n_iters,
+                   "fine_grid_iters_per_s": round(cfg["iters"][1] / np.mean(
+                       [r["seconds_per_grid"][1] for r in reps]), 3),
+                   "coarse_grid_iters_per_s": round(cfg["iters"][0] / np.mean(
+                       [r["seconds_per_grid"][0] for r in reps]), 3),
+                   "kernel_avg_ms": {KERNEL_NAMES[i]: round(avg_ms[i], 4) for i in range(3)},
+                   "kernel_share_fine_grid": {
+                       n: round(float(kms[i] / max(np.sum(kms), 1e-30)), 3)
+                       for i, n in enumerate(KERNEL_NAMES + ["other"])},
+                   "paper_context": "about 5 min for 512x512x70 on a Tesla C1060 "
+                                    "(different voxel size and 3-grid schedule; context only)"},
+        "roofline": roofline,
+    }
+    if not args.no_f16:
+        vol16, dt16, _ = run(tfcb.F16, args.steps, 1, False)
+        a = vol16.double()
+        b = vol32.double()
+        line["config"]["f16_storage"] = {
+            "value": round(n_iters * args.steps / dt16, 3), "unit": "TF iterations/s",
+            "ms_per_step": round(dt16 / args.steps * 1e3, 3),
+            "rel_l2_vs_f32": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, y)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -200,6 +200,30 @@ def framelet_shrink(f, lam, levels=1, positivity=True):
     return out
 
 
+def framelet_shrink_voxels(f, lam, kji, levels=1, positivity=True):
+    """``framelet_shrink`` evaluated at the listed voxels (k, j, i) only.
+
+    The operator is local: the output at a voxel depends on the coefficients
+    within distance d (dilation) of it, and those on the input within 2d, so
+    with one level it sees only the input within radius 2 (radius 6 with two
+    levels: 2 + 2 * 2).  Each voxel is evaluated by the oracle on a crop of
+    that radius whose faces are either faces of the volume (so the reflected
+    extension is the same) or at least the radius away from the voxel."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    rad = 2 if levels == 1 else 6
+    out = np.empty(len(kji), np.float64)
+    for q, (k, j, i) in enumerate(np.asarray(kji, dtype=np.int64)):
+        sl = []
+        ctr = []
+        for c, n in zip((k, j, i), f.shape):
+            lo, hi = max(0, c - rad), min(n, c + rad + 1)
+            sl.append(slice(lo, hi))
+            ctr.append(c - lo)
+        crop = np.ascontiguousarray(f[tuple(sl)])
+        out[q] = framelet_shrink(crop, lam, levels, positivity)[tuple(ctr)]
+    return out
+
+
 def cgls(g, x0, proj, n, history=False):
     """n CGLS steps warm-started from x0 (Appendix 1).  Returns
     (x, broke, resid2[, resid_hist])."""

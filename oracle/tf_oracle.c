@@ -292,27 +292,53 @@ static void free_op(op1d* o) {
 }
 
 /* out (+)= A in along one axis (axis 0 = x, 1 = y, 2 = z), or A^T in when
- * transpose is set.  Lines along the axis are independent. */
+ * transpose is set: element n of every line along the axis receives
+ * sum_e val * in[col] (A), or element col receives val * in[n] (A^T).  The
+ * innermost loop always runs over contiguous x; each thread owns whole
+ * lines (or rows) of the output, so there are no write races. */
 static void apply_axis(int nx, int ny, int nz, int axis, const op1d* A,
                        int transpose, const double* in, double* out, int accumulate) {
   int64_t nvox = (int64_t)nx * ny * nz;
   if (!accumulate) memset(out, 0, sizeof(double) * (size_t)nvox);
-  int N = axis == 0 ? nx : (axis == 1 ? ny : nz);
-  int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx : (int64_t)nx * ny);
-  int64_t nlines = nvox / N;
+  if (axis == 0) {
 #pragma omp parallel for schedule(static)
-  for (int64_t L = 0; L < nlines; ++L) {
-    int64_t base;
-    if (axis == 0) base = L * nx;
-    else if (axis == 1) base = (L / nx) * (int64_t)nx * ny + (L % nx);
-    else base = L;
-    for (int n = 0; n < N; ++n)
-      for (int e = 0; e < 3; ++e) {
-        int col = A->col[3 * n + e];
-        double v = A->val[3 * n + e];
-        if (!transpose) out[base + n * stride] += v * in[base + col * stride];
-        else out[base + col * stride] += v * in[base + n * stride];
-      }
+    for (int64_t L = 0; L < (int64_t)ny * nz; ++L) {
+      const double* a = in + L * nx;
+      double* b = out + L * nx;
+      for (int n = 0; n < nx; ++n)
+        for (int e = 0; e < 3; ++e) {
+          int col = A->col[3 * n + e];
+          double v = A->val[3 * n + e];
+          if (!transpose) b[n] += v * a[col];
+          else b[col] += v * a[n];
+        }
+    }
+  } else if (axis == 1) {
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z) {
+      const double* a = in + (int64_t)z * nx * ny;
+      double* b = out + (int64_t)z * nx * ny;
+      for (int n = 0; n < ny; ++n)
+        for (int e = 0; e < 3; ++e) {
+          int col = A->col[3 * n + e];
+          double v = A->val[3 * n + e];
+          int src = transpose ? n : col, dst = transpose ? col : n;
+          for (int i = 0; i < nx; ++i) b[(int64_t)dst * nx + i] += v * a[(int64_t)src * nx + i];
+        }
+    }
+  } else {
+    int64_t plane = (int64_t)nx * ny;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+      for (int n = 0; n < nz; ++n)
+        for (int e = 0; e < 3; ++e) {
+          int col = A->col[3 * n + e];
+          double v = A->val[3 * n + e];
+          int src = transpose ? n : col, dst = transpose ? col : n;
+          const double* a = in + src * plane + (int64_t)y * nx;
+          double* b = out + dst * plane + (int64_t)y * nx;
+          for (int i = 0; i < nx; ++i) b[i] += v * a[i];
+        }
   }
 }
 

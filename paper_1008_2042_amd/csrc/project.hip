@@ -1,0 +1,217 @@
+// Forward projector P: the line integral of Eq. (1) discretised by Joseph's
+// method, one thread per ray.
+//
+// Mapping: a 256-thread block covers 64 detector columns x 4 rows of one
+// view.  Each wavefront is one detector row; its 64 lanes are adjacent
+// columns, whose crossings with a plane of the stepping axis are adjacent in
+// the trans axis, which is the fastest axis of the volume copy the view
+// reads (native [z][y][x] for y-stepping views, [z][x][y] for x-stepping
+// views).  So the four bilinear taps of a plane are two short contiguous
+// runs per wavefront, and the four rows of a block share their z taps in L1.
+#include "tfcb_internal.h"
+
+namespace tfcb {
+
+// Planes [lo, hi] on which the ray may have a non-zero tap (with one plane of
+// margin; taps outside the grid get zero weight in the loop anyway).
+__device__ __forceinline__ void plane_range(const ColInfo& ci, float vz, float zc, int nt, int nz,
+                                            int& lo, int& hi) {
+  float a = (float)ci.p_lo, b = (float)ci.p_hi;
+  // trans: t0 + p dt in (-1, nt)
+  if (ci.dt != 0.f) {
+    float q1 = (-1.f - ci.t0) / ci.dt, q2 = ((float)nt - ci.t0) / ci.dt;
+    a = fmaxf(a, floorf(fminf(q1, q2)) - 1.f);
+    b = fminf(b, ceilf(fmaxf(q1, q2)) + 1.f);
+  } else if (!(ci.t0 > -1.f && ci.t0 < (float)nt)) {
+    b = a - 1.f;
+  }
+  // z: (tau0 + p dtau) vz + zc in (-1, nz)
+  const float z0 = fmaf(ci.tau0, vz, zc), dz = ci.dtau * vz;
+  if (dz != 0.f) {
+    float q1 = (-1.f - z0) / dz, q2 = ((float)nz - z0) / dz;
+    a = fmaxf(a, floorf(fminf(q1, q2)) - 1.f);
+    b = fminf(b, ceilf(fmaxf(q1, q2)) + 1.f);
+  } else if (!(z0 > -1.f && z0 < (float)nz)) {
+    b = a - 1.f;
+  }
+  lo = (int)a;
+  hi = (int)b;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __restrict__ views,
+                                                 const ColInfo* __restrict__ cols,
+                                                 const T* __restrict__ vol,
+                                                 const T* __restrict__ volT,
+                                                 const T* __restrict__ gin, T* __restrict__ out,
+                                                 T* __restrict__ rl, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int view = blockIdx.z;
+  const bool active = c < g.nu && r < g.nv;
+  double part = 0.0;
+  if (active) {
+    const ViewInfo vi = views[view];
+    const ColInfo ci = cols[(size_t)view * g.nu + c];
+    const T* __restrict__ v = vi.step_x ? volT : vol;
+    const int nt = vi.step_x ? g.ny : g.nx;
+    const int ns = vi.step_x ? g.nx : g.ny;
+    const int nz = g.nz;
+    const float vz = ((float)r - 0.5f * (float)(g.nv - 1)) * g.dvdz;
+    const float zc = 0.5f * (float)(nz - 1);
+    int lo, hi;
+    plane_range(ci, vz, zc, nt, nz, lo, hi);
+    float acc = 0.f;
+    for (int p = lo; p <= hi; ++p) {
+      const float fp = (float)p;
+      const float th = fmaf(fp, ci.dt, ci.t0);
+      const float tau = fmaf(fp, ci.dtau, ci.tau0);
+      const float zh = fmaf(tau, vz, zc);
+      const float tf = floorf(th), zf = floorf(zh);
+      const int it = (int)tf, iz = (int)zf;
+      float wt1 = th - tf, wz1 = zh - zf;
+      float wt0 = 1.f - wt1, wz0 = 1.f - wz1;
+      const bool t0ok = (unsigned)it < (unsigned)nt, t1ok = (unsigned)(it + 1) < (unsigned)nt;
+      const bool z0ok = (unsigned)iz < (unsigned)nz, z1ok = (unsigned)(iz + 1) < (unsigned)nz;
+      wt0 = t0ok ? wt0 : 0.f;
+      wt1 = t1ok ? wt1 : 0.f;
+      wz0 = z0ok ? wz0 : 0.f;
+      wz1 = z1ok ? wz1 : 0.f;
+      const int i0 = t0ok ? it : 0, i1 = t1ok ? it + 1 : 0;
+      const int k0 = z0ok ? iz : 0, k1 = z1ok ? iz + 1 : 0;
+      const int b0 = (k0 * ns + p) * nt, b1 = (k1 * ns + p) * nt;
+      const float v00 = ld(v + b0 + i0), v01 = ld(v + b0 + i1);
+      const float v10 = ld(v + b1 + i0), v11 = ld(v + b1 + i1);
+      acc += wz0 * fmaf(wt0, v00, wt1 * v01) + wz1 * fmaf(wt0, v10, wt1 * v11);
+    }
+    const float ell = ray_length(g, vi, ci, r);
+    const size_t o = ((size_t)view * g.nv + r) * g.nu + c;
+    const float val = ell * acc;
+    if (MODE == 0) {
+      st(out + o, val);
+    } else if (MODE == 1) {
+      const float res = ld(gin + o) - val;
+      st(out + o, res);
+      const float rs = ld(out + o);  // the stored (rounded) residual
+      st(rl + o, ell * rs);
+      part = (double)rs * (double)rs;
+    } else {
+      st(out + o, val);
+      const float qs = ld(out + o);
+      part = (double)qs * (double)qs;
+    }
+  }
+  if (MODE != 0) {
+    const double s = wave_block_sum(part, red);
+    if (threadIdx.x == 0)
+      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+int project_num_blocks(const GeomDev& g) {
+  return ((g.nu + 63) / 64) * ((g.nv + 3) / 4) * g.n_views;
+}
+
+template <typename T>
+hipError_t launch_project(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
+                          const T* vol, const T* volT, int mode, const T* gin, T* out, T* rl,
+                          double* partials, int* n_partials, hipStream_t s) {
+  dim3 block(256);
+  dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
+  if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_project<T, 0>), grid, block, 0, s, g, views, cols, vol, volT, gin, out,
+                       rl, partials);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_project<T, 1>), grid, block, 0, s, g, views, cols, vol, volT, gin, out,
+                       rl, partials);
+  else
+    hipLaunchKernelGGL((k_project<T, 2>), grid, block, 0, s, g, views, cols, vol, volT, gin, out,
+                       rl, partials);
+  return hipGetLastError();
+}
+
+// rl = l * in for every ray.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prescale(GeomDev g, const ViewInfo* __restrict__ views,
+                                                  const ColInfo* __restrict__ cols,
+                                                  const T* __restrict__ in, T* __restrict__ out) {
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int view = blockIdx.z;
+  if (c >= g.nu || r >= g.nv) return;
+  const ViewInfo vi = views[view];
+  const ColInfo ci = cols[(size_t)view * g.nu + c];
+  const size_t o = ((size_t)view * g.nv + r) * g.nu + c;
+  st(out + o, ray_length(g, vi, ci, r) * ld(in + o));
+}
+
+template <typename T>
+hipError_t launch_prescale(const GeomDev& g, const ColInfo* cols, const ViewInfo* views,
+                           const T* in, T* out, hipStream_t s) {
+  dim3 block(256);
+  dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
+  hipLaunchKernelGGL((k_prescale<T>), grid, block, 0, s, g, views, cols, in, out);
+  return hipGetLastError();
+}
+
+// r -= alpha q (skipped after a breakdown); rl = l * r; partial ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_update(GeomDev g,
+                                                         const ViewInfo* __restrict__ views,
+                                                         const ColInfo* __restrict__ cols,
+                                                         T* __restrict__ r, const T* __restrict__ q,
+                                                         T* __restrict__ rl,
+                                                         const CglsScalars* __restrict__ sc,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int row = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int view = blockIdx.z;
+  double part = 0.0;
+  if (c < g.nu && row < g.nv) {
+    const ViewInfo vi = views[view];
+    const ColInfo ci = cols[(size_t)view * g.nu + c];
+    const size_t o = ((size_t)view * g.nv + row) * g.nu + c;
+    float rv = ld(r + o);
+    if (!sc->stopped) {
+      rv = rv - (float)sc->alpha * ld(q + o);
+      st(r + o, rv);
+      rv = ld(r + o);
+    }
+    st(rl + o, ray_length(g, vi, ci, row) * rv);
+    part = (double)rv * (double)rv;
+  }
+  const double s = wave_block_sum(part, red);
+  if (threadIdx.x == 0)
+    partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+}
+
+template <typename T>
+hipError_t launch_residual_update(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
+                                  T* r, const T* q, T* rl, const CglsScalars* sc,
+                                  double* partials, int* n_partials, hipStream_t s) {
+  dim3 block(256);
+  dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
+  if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
+  hipLaunchKernelGGL((k_residual_update<T>), grid, block, 0, s, g, views, cols, r, q, rl, sc,
+                     partials);
+  return hipGetLastError();
+}
+
+#define TFCB_INST(T)                                                                            \
+  template hipError_t launch_project<T>(const GeomDev&, const ViewInfo*, const ColInfo*,         \
+                                        const T*, const T*, int, const T*, T*, T*, double*,     \
+                                        int*, hipStream_t);                                     \
+  template hipError_t launch_prescale<T>(const GeomDev&, const ColInfo*, const ViewInfo*,        \
+                                         const T*, T*, hipStream_t);                            \
+  template hipError_t launch_residual_update<T>(const GeomDev&, const ViewInfo*, const ColInfo*, \
+                                                T*, const T*, T*, const CglsScalars*, double*,   \
+                                                int*, hipStream_t);
+TFCB_INST(float)
+TFCB_INST(__half)
+TFCB_INST(__hip_bfloat16)
+#undef TFCB_INST
+
+}  // namespace tfcb

@@ -1,0 +1,112 @@
+"""The C-ABI library on the host (no GPU needed): it loads, exports every
+symbol include/tfcb.h declares, sizes workspaces, and rejects bad arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1008_2042_amd import inputs, tfcb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(tfcb.LIB_PATH):
+        pytest.skip("libtfcb.so not built (run __graft_entry__.build())")
+    return tfcb.load()
+
+
+def test_header_declarations_are_exported():
+    lib = _lib()
+    with open(os.path.join(ROOT, "include", "tfcb.h")) as fh:
+        hdr = fh.read()
+    declared = sorted(set(re.findall(r"\b(tfcb_[a-z_]+)\s*\(", hdr)))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(tfcb.EXPORTS) == declared
+
+
+def test_version_and_status_strings():
+    lib = _lib()
+    assert b"gfx950" in lib.tfcb_version()
+    assert lib.tfcb_status_str(0) == b"ok"
+    assert lib.tfcb_status_str(-2) == b"workspace too small"
+
+
+def test_workspace_sizes():
+    _lib()
+    g = inputs.config("paper")["geom"]
+    opts = tfcb.options(5e-4, [16, 24])
+    n = tfcb.workspace_size(g, opts)
+    V, S = 512 * 512 * 70 * 4, 40 * 384 * 512 * 4
+    # 7 volumes + 4 projection sets on the fine grid, plus the coarse grid
+    assert 7 * V + 4 * S <= n <= 1.3 * (7 * V + 4 * S)
+    n16 = tfcb.workspace_size(g, tfcb.options(5e-4, [16, 24], storage=tfcb.F16))
+    assert n16 < 0.55 * n
+    assert tfcb.operator_workspace_size(g, tfcb.F32) >= V
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("dz", -1.0), ("sdd", 500.0), ("n_views", 0),
+                                         ("sad", 100.0)])
+def test_bad_geometry_rejected(field, value):
+    lib = _lib()
+    g = inputs.config("paper")["geom"]
+    cg = tfcb.geometry(g)
+    setattr(cg, field, value)
+    n = ctypes.c_size_t(0)
+    st = lib.tfcb_operator_workspace_size(ctypes.byref(cg), 0, ctypes.byref(n))
+    assert st == tfcb.EINVAL
+    assert len(lib.tfcb_last_error()) > 0
+    # operator calls validate before any device work
+    st = lib.tfcb_project(ctypes.byref(cg), 0, 256, 256, 256, 1 << 30, None)
+    assert st == tfcb.EINVAL
+
+
+def test_bad_options_and_workspace_rejected():
+    lib = _lib()
+    g = tfcb.geometry(inputs.config("tiny")["geom"])
+    n = ctypes.c_size_t(0)
+    for kw in (dict(lam=-1.0), dict(lam=float("nan")), dict(iters=[1, 1, 1, 1, 1]),
+               dict(cgls_steps=0), dict(framelet_levels=3), dict(storage=7)):
+        args = dict(lam=5e-4, iters=[10], cgls_steps=3, framelet_levels=1, storage=0)
+        args.update(kw)
+        o = tfcb.options(args["lam"], args["iters"][:4], args["cgls_steps"],
+                         args["framelet_levels"], storage=args["storage"])
+        if len(args["iters"]) > 4:
+            o.n_grids = 5
+        assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) \
+            == tfcb.EINVAL, kw
+    o = tfcb.options(5e-4, [10])
+    assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == 0
+    # too small / misaligned / NULL workspace
+    st = lib.tfcb_reconstruct(ctypes.byref(g), ctypes.byref(o), 256, 256, 256, n.value - 1, None,
+                              None)
+    assert st == tfcb.ENOMEM
+    st = lib.tfcb_reconstruct(ctypes.byref(g), ctypes.byref(o), 256, 256, 257, n.value, None, None)
+    assert st == tfcb.EINVAL
+    st = lib.tfcb_reconstruct(ctypes.byref(g), ctypes.byref(o), None, 256, 256, n.value, None, None)
+    assert st == tfcb.EINVAL
+
+
+def test_framelet_argument_checks():
+    lib = _lib()
+    n = ctypes.c_size_t(0)
+    assert lib.tfcb_framelet_workspace_size(8, 8, 8, 1, 0, ctypes.byref(n)) == 0 and n.value == 0
+    assert lib.tfcb_framelet_workspace_size(8, 8, 8, 2, 0, ctypes.byref(n)) == 0 and n.value >= 4096
+    assert lib.tfcb_framelet_workspace_size(8, 8, 8, 3, 0, ctypes.byref(n)) == tfcb.EINVAL
+    # in == out is rejected
+    assert lib.tfcb_framelet_shrink(8, 8, 8, 1, 0.1, 1, 0, 256, 256, None, 0, None) == tfcb.EINVAL
+
+
+def test_product_path_does_not_reference_the_oracle():
+    """The GPU package never imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_1008_2042_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")) and f != "inputs.py":
+                with open(os.path.join(dirpath, f)) as fh:
+                    text = fh.read()
+                assert "import oracle" not in text and "tf_oracle" not in text, f

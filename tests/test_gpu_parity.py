@@ -1,0 +1,261 @@
+"""GPU parity: every operator of the HIP library, called through the C-ABI,
+against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2 unless noted): P and P^T 1e-4 per application, the
+fused framelet shrink 1e-5, restriction / prolongation 1e-6, CGLS 1e-4, the
+final FP32 volume 1e-3.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1008_2042_amd import inputs
+from paper_1008_2042_amd.inputs import Geometry
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1008_2042_amd import tfcb  # noqa: E402
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def announce(msg):
+    print("[gpu-case]", msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def t32(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+TINY = inputs.config("tiny")["geom"]
+# several tiles of every kernel plus ragged tails: 150 columns (64-wide
+# tiles), 37 rows (4-row tiles), 70 x 45 voxels (64 x 4 tiles), odd views
+# including the 45-degree stepping-axis tie and a reversed direction
+RAGGED = Geometry(70, 45, 9, 0.9, 1.1, 1.7, 150, 37, 0.8, 1.3, sad=300.0, sdd=450.0, n_views=7,
+                  angles=np.array([0.0, math.pi / 4, 1.0, 2.0, 3.0 * math.pi / 4, 4.0, 5.9]))
+DEGENERATE = Geometry(1, 3, 1, 1.0, 1.0, 1.0, 5, 1, 1.0, 1.0, sad=50.0, sdd=75.0, n_views=1)
+
+
+@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE], ids=["tiny", "ragged", "degenerate"])
+def test_project_parity(g):
+    dev = _dev()
+    f = inputs.random_volume(g, 1)
+    announce("project %s" % (g.vol_shape,))
+    got = host(tfcb.project(g, t32(f, dev)))
+    want = oracle.project(g, f)
+    assert rel(got, want) <= 1e-4
+
+
+@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE], ids=["tiny", "ragged", "degenerate"])
+def test_backproject_parity(g):
+    dev = _dev()
+    y = inputs.random_sino(g, 2)
+    announce("backproject %s" % (g.sino_shape,))
+    got = host(tfcb.backproject(g, t32(y, dev)))
+    want = oracle.backproject(g, y)
+    assert rel(got, want) <= 1e-4
+
+
+def test_adjoint_identity_gpu():
+    dev = _dev()
+    g = RAGGED
+    f = inputs.random_volume(g, 3)
+    y = inputs.random_sino(g, 4)
+    announce("adjoint identity")
+    pf = host(tfcb.project(g, t32(f, dev)))
+    pty = host(tfcb.backproject(g, t32(y, dev)))
+    lhs, rhs = float(np.vdot(pf, y)), float(np.vdot(f, pty))
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
+
+
+FRAMELET_SHAPES = [(16, 64, 64), (19, 33, 70), (1, 5, 7), (2, 1, 3), (3, 17, 31)]
+
+
+@pytest.mark.parametrize("shape", FRAMELET_SHAPES)
+@pytest.mark.parametrize("levels", [1, 2])
+def test_framelet_parity(shape, levels):
+    dev = _dev()
+    f = inputs.random_field(shape, 5, 0.0, 0.03)
+    lam = 4e-3
+    for pos in (True, False):
+        announce("framelet %s levels=%d positivity=%s" % (shape, levels, pos))
+        got = host(tfcb.framelet_shrink(t32(f, dev), lam, levels, pos))
+        want = oracle.framelet_shrink(f, lam, levels, pos)
+        assert rel(got, want) <= 1e-5, (shape, levels, pos)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_framelet_tight_frame_gpu(levels):
+    dev = _dev()
+    f = inputs.random_field((19, 33, 70), 6, -1.0, 1.0)
+    announce("framelet W^T W = I levels=%d" % levels)
+    got = host(tfcb.framelet_shrink(t32(f, dev), 0.0, levels, False))
+    assert rel(got, f) <= 1e-6
+
+
+def test_restrict_prolong_parity():
+    dev = _dev()
+    for g in (TINY, RAGGED):
+        y = inputs.random_sino(g, 7)
+        announce("restrict %s" % (g.sino_shape,))
+        got = host(tfcb.restrict_sino(g, t32(y, dev)))
+        assert rel(got, oracle.restrict_sino(g, y)) <= 1e-6
+        co = oracle.coarse_geom(g, True)
+        c = inputs.random_field((co.nz, co.ny, co.nx), 8, 0.0, 0.02)
+        announce("prolong %s" % (g.vol_shape,))
+        got = host(tfcb.prolong_vol(co, g, t32(c, dev)))
+        assert rel(got, oracle.prolong_vol(co, g, c)) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_cgls_parity(n):
+    dev = _dev()
+    cfg = inputs.config("tiny")
+    g = cfg["geom"]
+    y = inputs.measured_data(cfg)
+    x0 = inputs.random_volume(g, 9, 0.01)
+    announce("cgls n=%d" % n)
+    x = t32(x0, dev)
+    _, r2, broke = tfcb.cgls(g, x, t32(y, dev), n)
+    want, wbroke, wr2 = oracle.cgls(g, x0, y, n)
+    assert not broke and not wbroke
+    assert rel(host(x), want) <= 1e-4
+    assert abs(r2 - wr2) <= 1e-3 * wr2
+
+
+def test_cgls_breakdown_gpu():
+    """A consistent start (g = P x0 computed on the GPU) stops CGLS at once."""
+    dev = _dev()
+    g = TINY
+    x0 = t32(inputs.random_volume(g, 10), dev)
+    y = tfcb.project(g, x0)
+    x = x0.clone()
+    announce("cgls breakdown")
+    _, r2, broke = tfcb.cgls(g, x, y, 3)
+    # FP32 rounding leaves r ~ 1e-7 relative, so the guard need not fire;
+    # either way x must not move by more than rounding
+    assert rel(host(x), host(x0)) <= 1e-5
+    assert r2 <= 1e-8 * float(torch.sum(y.double() ** 2))
+
+
+def test_reconstruct_tiny_parity():
+    """The tiny workload: 64x64x16, 30 views, 10 iterations, lambda 5e-4."""
+    dev = _dev()
+    cfg = inputs.config("tiny")
+    g = cfg["geom"]
+    y = inputs.measured_data(cfg)
+    announce("reconstruct tiny")
+    got, rep = tfcb.reconstruct(g, t32(y, dev), cfg["lam"], cfg["iters"])
+    want, wrep = oracle.reconstruct(g, y, cfg["lam"], cfg["iters"])
+    assert rel(host(got), want) <= 1e-3
+    assert rep["resid2_last"] == pytest.approx(wrep["resid2_last"], rel=1e-2)
+    assert rep["iters_done"] == cfg["iters"]
+
+
+@pytest.mark.parametrize("momentum,levels", [(True, 1), (False, 1), (True, 2)])
+def test_reconstruct_two_grid_parity(momentum, levels):
+    dev = _dev()
+    g = Geometry(48, 40, 12, 1.5, 1.5, 1.5, 96, 48, 2.0, 2.0, n_views=20)
+    ells = inputs.tiny_phantom(11)
+    y = inputs.poisson_log(inputs.analytic_projection(g, ells), 1e5, 12)
+    announce("reconstruct two-grid momentum=%s levels=%d" % (momentum, levels))
+    got, rep = tfcb.reconstruct(g, t32(y, dev), 5e-4, [4, 3], momentum=momentum,
+                                framelet_levels=levels)
+    want, _ = oracle.reconstruct(g, y, 5e-4, [4, 3], momentum=momentum, framelet_levels=levels)
+    assert rel(host(got), want) <= 1e-3
+
+
+def test_reconstruct_deterministic():
+    dev = _dev()
+    cfg = inputs.config("tiny")
+    g = cfg["geom"]
+    y = t32(inputs.measured_data(cfg), dev)
+    announce("determinism")
+    a, _ = tfcb.reconstruct(g, y, cfg["lam"], [3])
+    b, _ = tfcb.reconstruct(g, y, cfg["lam"], [3])
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------- full size
+PAPER = inputs.config("paper")
+
+
+def test_paper_scale_project_sampled():
+    """512x512x70, 40 views, 512x384 detector: sampled rays vs the oracle."""
+    dev = _dev()
+    g = PAPER["geom"]
+    f = inputs.random_volume(g, 13)
+    announce("paper-scale project")
+    got = host(tfcb.project(g, t32(f, dev)))
+    rng = np.random.default_rng(14)
+    vrc = np.stack([rng.integers(0, g.n_views, 256), rng.integers(0, g.nv, 256),
+                    rng.integers(0, g.nu, 256)], axis=1)
+    want = oracle.project_rays(g, f, vrc)
+    assert rel(got[vrc[:, 0], vrc[:, 1], vrc[:, 2]], want) <= 1e-4
+
+
+def test_paper_scale_backproject_sampled():
+    dev = _dev()
+    g = PAPER["geom"]
+    y = inputs.random_sino(g, 15)
+    announce("paper-scale backproject")
+    got = host(tfcb.backproject(g, t32(y, dev)))
+    rng = np.random.default_rng(16)
+    kji = np.stack([rng.integers(0, g.nz, 48), rng.integers(0, g.ny, 48),
+                    rng.integers(0, g.nx, 48)], axis=1)
+    kji = np.concatenate([kji, [[0, 0, 0], [69, 511, 511], [35, 256, 0], [0, 255, 256]]])
+    want = oracle.backproject_voxels(g, y, kji)
+    assert rel(got[kji[:, 0], kji[:, 1], kji[:, 2]], want) <= 1e-4
+
+
+def test_paper_scale_framelet_sampled():
+    dev = _dev()
+    g = PAPER["geom"]
+    f = inputs.random_volume(g, 17)
+    announce("paper-scale framelet")
+    got = host(tfcb.framelet_shrink(t32(f, dev), 4e-3, 1, True))
+    rng = np.random.default_rng(18)
+    kji = np.stack([rng.integers(0, g.nz, 64), rng.integers(0, g.ny, 64),
+                    rng.integers(0, g.nx, 64)], axis=1)
+    kji = np.concatenate([kji, [[0, 0, 0], [69, 511, 511], [34, 29, 30], [35, 14, 511]]])
+    want = oracle.framelet_shrink_voxels(f, 4e-3, kji, 1, True)
+    assert rel(got[kji[:, 0], kji[:, 1], kji[:, 2]], want) <= 1e-5
+
+
+def test_paper_scale_reconstruct_properties():
+    """The benchmark's configuration end to end: finite, non-negative,
+    repeatable bit for bit, and the residual ends far below ||g||^2."""
+    dev = _dev()
+    g = PAPER["geom"]
+    y = inputs.measured_data(PAPER)
+    yt = t32(y, dev)
+    announce("paper-scale reconstruct")
+    a, rep = tfcb.reconstruct(g, yt, PAPER["lam"], PAPER["iters"])
+    b, _ = tfcb.reconstruct(g, yt, PAPER["lam"], PAPER["iters"])
+    assert torch.equal(a, b)
+    v = host(a)
+    assert np.all(np.isfinite(v)) and v.min() >= 0.0
+    assert rep["resid2_last"] < 0.05 * float(np.sum(y ** 2))
+    truth_mean = 0.02  # body attenuation
+    body = v[30:40, 200:312, 200:312]
+    assert abs(body.mean() - truth_mean) < 0.005

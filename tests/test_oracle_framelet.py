@@ -169,3 +169,16 @@ def test_filters_match_paper_constants():
         np.array(h[n]["taps"]) * _SCALE[h[n]["scale"]], (-1, 0, 1)))) ** 2
         for n in ("h0", "h1", "h2"))
     np.testing.assert_allclose(s, 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_sampled_framelet_equals_full(levels):
+    """The crop evaluation (locality radius 2, or 6 with two levels) reproduces
+    the full-volume oracle exactly, at interior and boundary voxels."""
+    f = random_field((9, 14, 15), 17, 0.0, 0.03)
+    lam = 4e-3
+    full = oracle.framelet_shrink(f, lam, levels, True)
+    kji = [(0, 0, 0), (4, 7, 7), (8, 13, 14), (1, 2, 13), (8, 6, 0), (3, 10, 5)]
+    got = oracle.framelet_shrink_voxels(f, lam, kji, levels, True)
+    want = np.array([full[k, j, i] for k, j, i in kji])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
