@@ -182,6 +182,53 @@ tfcb_status tfcb_reconstruct(const tfcb_geometry* g, const tfcb_options* o, cons
                              float* vol, void* ws, size_t ws_bytes, void* stream,
                              tfcb_report* report);
 
+/* ---------------------------------------------------------------- serving */
+/* Continuous batching of whole reconstructions (the method of
+ * tfcb_reconstruct, per request).  Requests of any geometry and options are
+ * submitted at any time and admitted in arrival order as soon as one of
+ * max_slots slots is free and the request's workspace (tfcb_request_bytes)
+ * fits in the caller-owned device arena; each admitted request keeps all of
+ * its state on the device, runs on its own stream, and advances one outer
+ * iteration per tfcb_server_step, so the iterations of concurrent requests
+ * overlap on the GPU.  A request's result is bitwise identical to
+ * tfcb_reconstruct of the same input, alone or in any mix.
+ *
+ * Ownership: the arena (device, 256-byte aligned) is the caller's and must
+ * outlive the server; the server owns its streams, events and a few bytes
+ * of pinned host memory, released by tfcb_server_destroy.  proj (device
+ * FP32 projections) and vol (device FP32 output) of a submitted request are
+ * read/written until the request is DONE, FAILED or CANCELLED.  A server
+ * handle is not thread-safe. */
+typedef struct tfcb_server tfcb_server;
+#define TFCB_REQ_QUEUED 0
+#define TFCB_REQ_RUNNING 1
+#define TFCB_REQ_DONE 2
+#define TFCB_REQ_FAILED 3    /* result holds the status, e.g. TFCB_ENUMERIC */
+#define TFCB_REQ_CANCELLED 4
+
+/* Device bytes one request occupies in the arena. */
+tfcb_status tfcb_request_bytes(const tfcb_geometry* g, const tfcb_options* o, size_t* bytes);
+/* max_slots: 1..64 requests in flight at once. */
+tfcb_status tfcb_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
+                               tfcb_server** out);
+/* Validates and queues a request; TFCB_ENOMEM if it can never fit the arena.
+ * id: HOST output. */
+tfcb_status tfcb_server_submit(tfcb_server* s, const tfcb_geometry* g, const tfcb_options* o,
+                               const float* proj, float* vol, uint64_t* id);
+/* Non-blocking: retires finished requests, admits queued ones, and enqueues
+ * the next outer iteration of each active request (at most two iterations
+ * ahead of the device per request).  n_active, n_queued: nullable HOST. */
+tfcb_status tfcb_server_step(tfcb_server* s, int32_t* n_active, int32_t* n_queued);
+/* state: TFCB_REQ_*; t_done: completion time in seconds of the host's
+ * monotonic clock (CLOCK_MONOTONIC), from the device's completion event;
+ * result: the request's status.  All nullable HOST. */
+tfcb_status tfcb_server_poll(tfcb_server* s, uint64_t id, int32_t* state, double* t_done,
+                             tfcb_status* result);
+/* Cancels a queued or running request (waits for its in-flight kernels). */
+tfcb_status tfcb_server_cancel(tfcb_server* s, uint64_t id);
+/* Waits for all in-flight work, then frees the handle. */
+tfcb_status tfcb_server_destroy(tfcb_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,12 +75,21 @@ inline GeomDev make_geom_dev(const tfcb_geometry& g) {
 
 // ------------------------------------------------------- device scalars
 // CGLS state kept on the device so no iteration needs a host round trip.
+//
+// The search direction is stored normalised, pn = p / sigma with sigma the
+// rms of the latest s = P^T r, so P pn stays O(planes) whatever the scale of
+// the data (FP16 storage would otherwise overflow).  CGLS is invariant to
+// that scaling: with qn = P pn, alpha p = (gamma / (sigma ||qn||^2)) pn and
+// alpha q = the same factor times qn, and the next direction is
+// pn' = (s' + beta sigma pn) / sigma'.
 struct CglsScalars {
-  double gamma;   // ||s||^2 of the current direction
-  double delta;   // ||q||^2
-  double alpha;
-  double beta;
-  double resid2;  // latest ||r||^2
+  double gamma;      // ||s||^2 of the current direction
+  double delta;      // ||q||^2 = sigma^2 ||qn||^2
+  double sigma;      // scale of the stored direction
+  double alpha;      // step applied to pn and qn: gamma / (sigma ||qn||^2)
+  double beta_sigma; // beta * sigma, the weight of the old pn in the new one
+  double inv_sigma;  // 1 / sigma of the new direction
+  double resid2;     // latest ||r||^2
   int32_t stopped;     // breakdown guard fired in this CGLS call
   int32_t breakdowns;  // number of CGLS calls stopped so far
 };
@@ -154,14 +163,16 @@ hipError_t launch_lowpass(int nx, int ny, int nz, const T* in, T* low, hipStream
 
 // CGLS vector kernels.
 enum FinalizeMode { FIN_GAMMA_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RESID = 3 };
+// nvox: voxel count of the grid (sigma = sqrt(gamma / nvox)).
 hipError_t launch_finalize(const double* partials, int n, int mode, CglsScalars* sc,
-                           hipStream_t s);
+                           double nvox, hipStream_t s);
 template <typename T>
 hipError_t launch_residual_update(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
                                   T* r, const T* q, T* rl, const CglsScalars* sc,
                                   double* partials, int* n_partials, hipStream_t s);
-// mode 0: p = s (and pT).  mode 1: x += alpha p; p = s + beta p (and pT).
-// mode 2: x += alpha p only.
+// Normalised direction pn (see CglsScalars).  mode 0: pn = s / sigma (s may
+// alias p) and pT.  mode 1: x += alpha pn; pn = (s + beta_sigma pn) / sigma'
+// and pT.  mode 2: x += alpha pn only.
 template <typename T>
 hipError_t launch_xp_update(int nx, int ny, int nz, int mode, T* x, T* p, T* pT, const T* s,
                             const CglsScalars* sc, hipStream_t s_);

@@ -9,7 +9,8 @@ namespace tfcb {
 // ------------------------------------------------------------- reductions
 __global__ __launch_bounds__(kReduceThreads) void k_finalize(const double* __restrict__ partials,
                                                              int n, int mode,
-                                                             CglsScalars* __restrict__ sc) {
+                                                             CglsScalars* __restrict__ sc,
+                                                             double nvox) {
   __shared__ double red[kReduceThreads / 64];
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += kReduceThreads) v += partials[i];
@@ -17,30 +18,47 @@ __global__ __launch_bounds__(kReduceThreads) void k_finalize(const double* __res
   if (threadIdx.x != 0) return;
   const double tiny = 1e-300;
   switch (mode) {
-    case FIN_GAMMA_INIT:
+    case FIN_GAMMA_INIT: {
+      // s = P^T r of a new CGLS call; the first direction is s / sigma
       sc->gamma = sum;
       sc->stopped = 0;
       sc->alpha = 0.0;
-      sc->beta = 0.0;
+      sc->beta_sigma = 0.0;
+      const double sig = sqrt(sum / nvox);
+      sc->sigma = sig > 0.0 ? sig : 1.0;
+      sc->inv_sigma = 1.0 / sc->sigma;
       break;
-    case FIN_ALPHA:
-      sc->delta = sum;
-      if (sc->stopped || sc->gamma <= tiny || sum <= tiny) {
+    }
+    case FIN_ALPHA: {
+      // sum = ||qn||^2; ||q||^2 = sigma^2 ||qn||^2
+      const double delta = sc->sigma * sc->sigma * sum;
+      sc->delta = delta;
+      if (sc->stopped || sc->gamma <= tiny || delta <= tiny) {
         if (!sc->stopped) sc->breakdowns += 1;
         sc->stopped = 1;
         sc->alpha = 0.0;
       } else {
-        sc->alpha = sc->gamma / sum;
+        sc->alpha = sc->gamma / (sc->sigma * sum);
       }
       break;
-    case FIN_BETA:
+    }
+    case FIN_BETA: {
+      // sum = ||s'||^2: beta = gamma' / gamma, pn' = (s' + beta sigma pn) / sigma'
       if (sc->stopped) {
-        sc->beta = 0.0;
+        sc->beta_sigma = 0.0;
+        sc->inv_sigma = 1.0 / sc->sigma;
       } else {
-        sc->beta = sum / sc->gamma;
+        // with sigma' = rms(s') the two terms of pn' = s'/sigma' +
+        // (sigma'/sigma) pn are both O(1): beta sigma / sigma' = sigma'/sigma
+        const double beta = sum / sc->gamma;
+        sc->beta_sigma = beta * sc->sigma;
+        const double sig = sqrt(sum / nvox);
+        sc->sigma = sig > 0.0 ? sig : 1.0;
+        sc->inv_sigma = 1.0 / sc->sigma;
         sc->gamma = sum;
       }
       break;
+    }
     default:
       sc->resid2 = sum;
       break;
@@ -48,8 +66,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_finalize(const double* __res
 }
 
 hipError_t launch_finalize(const double* partials, int n, int mode, CglsScalars* sc,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kReduceThreads), 0, s, partials, n, mode, sc);
+                           double nvox, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kReduceThreads), 0, s, partials, n, mode, sc,
+                     nvox);
   return hipGetLastError();
 }
 
@@ -57,8 +76,10 @@ __global__ void k_cgls_reset(CglsScalars* sc) {
   if (threadIdx.x == 0) {
     sc->gamma = 0.0;
     sc->delta = 0.0;
+    sc->sigma = 1.0;
     sc->alpha = 0.0;
-    sc->beta = 0.0;
+    sc->beta_sigma = 0.0;
+    sc->inv_sigma = 1.0;
     sc->resid2 = 0.0;
     sc->stopped = 0;
     sc->breakdowns = 0;
@@ -76,14 +97,14 @@ hipError_t launch_cgls_reset(CglsScalars* sc, hipStream_t s) {
 // written with full rows.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_xp_update(int nx, int ny, T* __restrict__ x,
-                                                   T* __restrict__ p, T* __restrict__ pT,
-                                                   const T* __restrict__ s,
+                                                   T* p, T* __restrict__ pT, const T* s,
                                                    const CglsScalars* __restrict__ sc) {
   __shared__ float tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
   const bool stopped = sc->stopped != 0;
-  const float alpha = (float)sc->alpha, beta = (float)sc->beta;
+  const float alpha = (float)sc->alpha, beta_sigma = (float)sc->beta_sigma;
+  const float inv_sigma = (float)sc->inv_sigma;
   const size_t zoff = (size_t)z * nx * ny;
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
@@ -92,11 +113,11 @@ __global__ __launch_bounds__(256) void k_xp_update(int nx, int ny, T* __restrict
       const size_t o = zoff + (size_t)yy * nx + xx;
       float pn;
       if (MODE == 0) {
-        pn = ld(s + o);
+        pn = ld(s + o) * inv_sigma;
       } else {
         const float pv = ld(p + o);
         if (!stopped) st(x + o, fmaf(alpha, pv, ld(x + o)));
-        pn = (MODE == 1) ? fmaf(beta, pv, ld(s + o)) : pv;
+        pn = (MODE == 1) ? fmaf(beta_sigma, pv, ld(s + o)) * inv_sigma : pv;
       }
       if (MODE != 2) {
         st(p + o, pn);

@@ -91,7 +91,7 @@ def serving_geometry(nxy: int, nz: int, n_views: int) -> Geometry:
     """Serving-mix geometry: 256 mm in-plane FOV, 175 mm z-FOV for 70-slice
     volumes (z voxel 2.5 mm), detector nu = nx, nv = 3/4 nx at 0.776*512/nx mm."""
     dxy = 256.0 / nxy
-    dz = 2.5 if nz in (70,) else (175.0 / nz)
+    dz = 175.0 / nz
     pitch = 0.776 * 512.0 / nxy
     return Geometry(nxy, nxy, nz, dxy, dxy, dz, nxy, (3 * nxy) // 4, pitch, pitch,
                     n_views=n_views)
@@ -212,6 +212,71 @@ def analytic_projection(g: Geometry, ellipsoids: List[Ellipsoid]) -> np.ndarray:
         src, a = _scanner_rays(g, k)
         for e in ellipsoids:
             out[k] += chord(src, a, e)
+    return out
+
+
+def analytic_projection_torch(g: Geometry, ellipsoids: List[Ellipsoid], device):
+    """The same exact chord integrals as analytic_projection, evaluated in
+    FP64 with torch on `device` (fast generation of large serving mixes)."""
+    import torch
+    f64 = torch.float64
+    th = torch.tensor(g.view_angles(), dtype=f64, device=device)
+    ct, st = torch.cos(th)[:, None, None], torch.sin(th)[:, None, None]
+    u = ((torch.arange(g.nu, dtype=f64, device=device) - 0.5 * (g.nu - 1)) * g.du)[None, None, :]
+    v = ((torch.arange(g.nv, dtype=f64, device=device) - 0.5 * (g.nv - 1)) * g.dv)[None, :, None]
+    sx, sy = g.sad * ct, g.sad * st
+    px = -(g.sdd - g.sad) * ct - u * st
+    py = -(g.sdd - g.sad) * st + u * ct
+    ax = (px - sx).expand(g.n_views, g.nv, g.nu)
+    ay = (py - sy).expand(g.n_views, g.nv, g.nu)
+    az = v.expand(g.n_views, g.nv, g.nu)
+    alen = torch.sqrt(ax * ax + ay * ay + az * az)
+    out = torch.zeros((g.n_views, g.nv, g.nu), dtype=f64, device=device)
+    for e in ellipsoids:
+        c, s = math.cos(e.phi), math.sin(e.phi)
+        a0, a1, a2 = (float(x) for x in e.axes)
+        ox, oy, oz = (sx - e.center[0]), (sy - e.center[1]), -float(e.center[2])
+        # rotate into the ellipsoid frame (x R with R = [[c, -s], [s, c]]), scale by axes
+        p0, p1, p2 = (ox * c + oy * s) / a0, (-ox * s + oy * c) / a1, oz / a2
+        q0, q1, q2 = (ax * c + ay * s) / a0, (-ax * s + ay * c) / a1, az / a2
+        A = q0 * q0 + q1 * q1 + q2 * q2
+        B = q0 * p0 + q1 * p1 + q2 * p2
+        C = p0 * p0 + p1 * p1 + p2 * p2 - 1.0
+        disc = B * B - A * C
+        hit = disc > 0
+        sq = torch.sqrt(torch.where(hit, disc, torch.zeros_like(disc)))
+        t1 = torch.clamp((-B - sq) / A, 0.0, 1.0)
+        t2 = torch.clamp((-B + sq) / A, 0.0, 1.0)
+        out += torch.where(hit, (t2 - t1) * alen * e.rho, torch.zeros_like(disc))
+    return out
+
+
+def poisson_log_torch(g_true, i0: float, seed: int):
+    """-ln(max(I, 1) / I0) with I ~ Poisson(I0 exp(-g)), seeded torch generator
+    on the tensor's device."""
+    import torch
+    gen = torch.Generator(device=g_true.device)
+    gen.manual_seed(int(seed))
+    counts = torch.poisson(i0 * torch.exp(-g_true), generator=gen)
+    return -torch.log(torch.clamp(counts, min=1.0) / i0)
+
+
+SERVING_SIZES = [(128, 128), (256, 48), (256, 96), (512, 70)]  # (nxy, nz)
+SERVING_VIEWS = [20, 40, 60, 120]
+SERVING_I0 = [1e4, 1e5]
+
+
+def serving_mix(n: int = 64, seed: int = 404):
+    """Seeded request mix: size, views and dose drawn uniformly from the
+    serving sets; phantom seed 4000 + i (body + 4 bone + 15 soft inserts)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        nxy, nz = SERVING_SIZES[int(rng.integers(len(SERVING_SIZES)))]
+        views = SERVING_VIEWS[int(rng.integers(len(SERVING_VIEWS)))]
+        i0 = SERVING_I0[int(rng.integers(len(SERVING_I0)))]
+        out.append(dict(index=i, geom=serving_geometry(nxy, nz, views), i0=i0,
+                        phantom_seed=4000 + i, noise_seed=5000 + i))
     return out
 
 

@@ -25,7 +25,10 @@ EXPORTS = [
     "tfcb_workspace_size", "tfcb_operator_workspace_size", "tfcb_framelet_workspace_size",
     "tfcb_project", "tfcb_backproject", "tfcb_framelet_shrink", "tfcb_cgls",
     "tfcb_restrict_sino", "tfcb_prolong_vol", "tfcb_reconstruct",
+    "tfcb_request_bytes", "tfcb_server_create", "tfcb_server_submit", "tfcb_server_step",
+    "tfcb_server_poll", "tfcb_server_cancel", "tfcb_server_destroy",
 ]
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
 class TfcbError(RuntimeError):
@@ -88,6 +91,14 @@ def load(path: str = LIB_PATH):
         "tfcb_restrict_sino": ([G, i32, vp, vp, vp], i32),
         "tfcb_prolong_vol": ([G, G, i32, vp, vp, vp], i32),
         "tfcb_reconstruct": ([G, O, vp, vp, vp, sz, vp, ctypes.POINTER(Report)], i32),
+        "tfcb_request_bytes": ([G, O, psz], i32),
+        "tfcb_server_create": ([vp, sz, i32, ctypes.POINTER(vp)], i32),
+        "tfcb_server_submit": ([vp, G, O, vp, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
+        "tfcb_server_step": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "tfcb_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(dbl),
+                              ctypes.POINTER(i32)], i32),
+        "tfcb_server_cancel": ([vp, ctypes.c_uint64], i32),
+        "tfcb_server_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -273,3 +284,68 @@ def reconstruct(g, proj, lam: float, iters: Sequence[int], cgls_steps: int = 3,
               "cgls_breakdowns": rep.cgls_breakdowns,
               "kernel_ms": list(rep.kernel_ms), "kernel_launches": list(rep.kernel_launches)}
     return out, report
+
+
+class Server:
+    """Continuous-batching reconstruction server over a device arena (see the
+    serving section of include/tfcb.h).  Submitted tensors are kept alive by
+    this object until their request ends."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 8, device=None):
+        torch = _torch()
+        self.device = device or torch.device("cuda:0")
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(load().tfcb_server_create(_ptr(self.arena), int(arena_bytes), int(max_slots),
+                                         ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def request_bytes(g, opts: Options) -> int:
+        n = ctypes.c_size_t(0)
+        _check(load().tfcb_request_bytes(ctypes.byref(geometry(g)), ctypes.byref(opts),
+                                         ctypes.byref(n)))
+        return n.value
+
+    def submit(self, g, proj, opts: Options, out=None) -> int:
+        torch = _torch()
+        if out is None:
+            out = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=proj.device)
+        rid = ctypes.c_uint64(0)
+        _check(load().tfcb_server_submit(self._h, ctypes.byref(geometry(g)), ctypes.byref(opts),
+                                         _ptr(proj), _ptr(out), ctypes.byref(rid)))
+        self._keep[rid.value] = (proj, out)
+        return rid.value
+
+    def step(self):
+        a, q = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(load().tfcb_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, rid: int):
+        st, res = ctypes.c_int32(0), ctypes.c_int32(0)
+        t = ctypes.c_double(0.0)
+        _check(load().tfcb_server_poll(self._h, int(rid), ctypes.byref(st), ctypes.byref(t),
+                                       ctypes.byref(res)))
+        return st.value, t.value, res.value
+
+    def result(self, rid: int):
+        return self._keep[rid][1]
+
+    def release(self, rid: int):
+        self._keep.pop(rid, None)
+
+    def cancel(self, rid: int):
+        _check(load().tfcb_server_cancel(self._h, int(rid)))
+
+    def close(self):
+        if self._h is not None:
+            _check(load().tfcb_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -93,3 +93,19 @@ def test_oracle_projection_of_voxelised_ellipsoids():
         errs.append(np.linalg.norm((got - want)[hit]) / np.linalg.norm(want[hit]))
     # discontinuous edges: first-order convergence (measured 5.3 % -> 2.4 %)
     assert errs[0] < 0.07 and errs[1] < 0.6 * errs[0], errs
+
+
+def test_torch_generator_matches_numpy():
+    torch = pytest.importorskip("torch")
+    g = inputs.serving_geometry(128, 128, 6)
+    ells = inputs.body_phantom(4001, 4, 15)
+    want = inputs.analytic_projection(g, ells)
+    got = inputs.analytic_projection_torch(g, ells, torch.device("cpu")).numpy()
+    # rounding only (grazing rays amplify it through the square root)
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-10)
+    mix = inputs.serving_mix(64)
+    assert len(mix) == 64 and len({m["geom"].nx for m in mix}) == 3
+    assert {m["geom"].n_views for m in mix} <= set(inputs.SERVING_VIEWS)
+    y = inputs.poisson_log_torch(torch.tensor(want), 1e4, 3)
+    y2 = inputs.poisson_log_torch(torch.tensor(want), 1e4, 3)
+    assert torch.equal(y, y2)
