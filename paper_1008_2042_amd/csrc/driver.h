@@ -71,6 +71,11 @@ tfcb_status validate_geometry(const tfcb_geometry* g) {
     return fail(TFCB_EUNSUPPORTED, "volume or projection set exceeds 2^31 elements");
   if (g->nx > 65535 || g->ny > 65535 || g->nz > 65535 || g->n_views > 65535)
     return fail(TFCB_EUNSUPPORTED, "an axis exceeds 65535");
+  if (g->nv > 16384 || g->nu > 65535)
+    return fail(TFCB_EUNSUPPORTED, "detector larger than 65535 x 16384 pixels");
+  const double pad = (double)(g->nz + 2) * std::max(g->nx, g->ny) * (std::max(g->nx, g->ny) + 1);
+  if (pad >= 2147483647.0)
+    return fail(TFCB_EUNSUPPORTED, "padded volume copy exceeds 2^31 elements");
   if (g->angles)
     for (int k = 0; k < g->n_views; ++k)
       if (!std::isfinite(g->angles[k])) return fail(TFCB_EINVAL, "angle %d is not finite", k);
@@ -151,8 +156,11 @@ struct GridBufs {
   GeomDev gd;
   ViewInfo* views;
   ColInfo* cols;
-  void *x0, *x1, *p, *pT, *s, *f0, *f1;  // volumes
-  void *g, *r, *rl, *q;                  // projections
+  void *x0, *x1, *s, *f0, *f1;  // volumes [z][y][x]
+  void *pN, *pT;                // CGLS direction: padded native / transposed copies
+  void* t2;                     // second framelet scratch (two levels only)
+  size_t pN_elems, pT_elems;
+  void *g, *r, *rl, *q;         // projections
   double* partials;
   int max_partials;
 };
@@ -186,9 +194,12 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
     const size_t V = nvox(cur) * es, S = npix(cur) * es;
     b.x0 = cv.take(V);
     b.x1 = cv.take(V);
-    b.p = cv.take(V);
-    b.pT = cv.take(V);
+    b.pN_elems = pad_elems(cur.ny, cur.nx, cur.nz);
+    b.pT_elems = pad_elems(cur.nx, cur.ny, cur.nz);
+    b.pN = cv.take(b.pN_elems * es);
+    b.pT = cv.take(b.pT_elems * es);
     b.s = cv.take(V);
+    b.t2 = o.framelet_levels == 2 ? cv.take(V) : nullptr;
     b.f0 = cv.take(V);
     b.f1 = cv.take(V);
     b.g = cv.take(S);
@@ -201,9 +212,13 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
   P.bytes = cv.off;
 }
 
-// Device-side tables of one grid (angles already on the device or NULL).
-tfcb_status setup_tables(const GridBufs& b, const double* angles_dev, hipStream_t s) {
+// Device-side tables of one grid (angles already on the device or NULL),
+// and the zero pads of its padded direction copies (never written later).
+template <typename T>
+tfcb_status setup_grid(const GridBufs& b, const double* angles_dev, hipStream_t s) {
   TFCB_HIP(launch_geom_tables(b.geom, angles_dev, b.views, b.cols, s));
+  TFCB_HIP(launch_fill(b.pN_elems, 0.f, static_cast<T*>(b.pN), s));
+  TFCB_HIP(launch_fill(b.pT_elems, 0.f, static_cast<T*>(b.pT), s));
   return TFCB_OK;
 }
 
@@ -262,7 +277,7 @@ template <typename T>
 tfcb_status run_cgls(const GridBufs& b, CglsScalars* sc, T* x, const T* gin, int n,
                      hipStream_t s, Profiler* prof = nullptr) {
   const GeomDev& g = b.gd;
-  T* p = static_cast<T*>(b.p);
+  T* pN = static_cast<T*>(b.pN);
   T* pT = static_cast<T*>(b.pT);
   T* sv = static_cast<T*>(b.s);
   T* r = static_cast<T*>(b.r);
@@ -270,19 +285,21 @@ tfcb_status run_cgls(const GridBufs& b, CglsScalars* sc, T* x, const T* gin, int
   T* q = static_cast<T*>(b.q);
   int np = 0;
   const double nv = (double)g.nx * g.ny * g.nz;
-  // r = g - P x; rl = l r
-  TFCB_HIP(launch_transpose_xy(g.nx, g.ny, g.nz, x, pT, s));
-  TFCB_TIMED(prof, 0, launch_project(g, b.views, b.cols, x, pT, 1, gin, r, rl, b.partials, &np, s));
+  // r = g - P x; rl = l r   (x reaches P through the padded copies)
+  TFCB_HIP(launch_pad_copies(g.nx, g.ny, g.nz, (const T*)x, pN, pT, s));
+  TFCB_TIMED(prof, 0, launch_project(g, b.views, b.cols, (const T*)pN, (const T*)pT, 1, gin, r,
+                                     rl, b.partials, &np, s));
   TFCB_HIP(launch_finalize(b.partials, np, FIN_RESID, sc, nv, s));
-  // p = s = P^T r; gamma = ||s||^2
-  TFCB_TIMED(prof, 1, launch_backproject(g, b.views, b.cols, rl, p, b.partials, &np, s));
+  // s = P^T r; gamma = ||s||^2
+  TFCB_TIMED(prof, 1, launch_backproject(g, b.views, b.cols, rl, sv, b.partials, &np, s));
   TFCB_HIP(launch_finalize(b.partials, np, FIN_GAMMA_INIT, sc, nv, s));
-  // pn = s / sigma in place, and its [z][x][y] copy
-  TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 0, x, p, pT, (const T*)p, sc, s));
+  // pn = s / sigma, as its two padded copies
+  TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 0, x, pN, pT, (const T*)sv, sc, s));
   for (int l = 0; l < n; ++l) {
     // q = P p; alpha = gamma / ||q||^2 (or stop)
-    TFCB_TIMED(prof, 0, launch_project(g, b.views, b.cols, p, pT, 2, static_cast<const T*>(nullptr), q,
-                            static_cast<T*>(nullptr), b.partials, &np, s));
+    TFCB_TIMED(prof, 0, launch_project(g, b.views, b.cols, (const T*)pN, (const T*)pT, 2,
+                                       static_cast<const T*>(nullptr), q,
+                                       static_cast<T*>(nullptr), b.partials, &np, s));
     TFCB_HIP(launch_finalize(b.partials, np, FIN_ALPHA, sc, nv, s));
     // r -= alpha q; rl = l r
     TFCB_HIP(launch_residual_update(g, b.views, b.cols, r, q, rl, sc, b.partials, &np, s));
@@ -291,9 +308,9 @@ tfcb_status run_cgls(const GridBufs& b, CglsScalars* sc, T* x, const T* gin, int
       // s = P^T r; beta = ||s||^2 / gamma; x += alpha p; p = s + beta p
       TFCB_TIMED(prof, 1, launch_backproject(g, b.views, b.cols, rl, sv, b.partials, &np, s));
       TFCB_HIP(launch_finalize(b.partials, np, FIN_BETA, sc, nv, s));
-      TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 1, x, p, pT, (const T*)sv, sc, s));
+      TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 1, x, pN, pT, (const T*)sv, sc, s));
     } else {
-      TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 2, x, p, pT, (const T*)sv, sc, s));
+      TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 2, x, pN, pT, (const T*)sv, sc, s));
     }
   }
   return TFCB_OK;
@@ -341,7 +358,7 @@ tfcb_status reconstruct_t(const tfcb_geometry& g, const tfcb_options& o, const f
   TFCB_TRY(upload_angles(g, P.angles, s, &ang));
   TFCB_HIP(launch_cgls_reset(P.sc, s));
   const int ng = o.n_grids;
-  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_tables(P.grid[l], ang, s));
+  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_grid<T>(P.grid[l], ang, s));
   // projections of every grid: the finest converted to the storage type,
   // coarser ones binned (or copied) from the next finer
   TFCB_HIP((launch_cast<float, T>(npix(g), proj, static_cast<T*>(P.grid[0].g), s)));
@@ -390,7 +407,7 @@ tfcb_status reconstruct_t(const tfcb_geometry& g, const tfcb_options& o, const f
       TFCB_TRY(run_cgls<T>(b, P.sc, xa, static_cast<const T*>(b.g), o.cgls_steps, s, pf));
       TFCB_TRY(run_framelet<T>(gg, o.framelet_levels, (float)o.lambda, o.positivity, xa, f_nxt,
                                f_cur, xb, (float)mom[k + 1], static_cast<T*>(b.s),
-                               static_cast<T*>(b.pT), s, pf));
+                               static_cast<T*>(b.t2), s, pf));
       std::swap(f_cur, f_nxt);
       std::swap(xa, xb);
     }
@@ -442,7 +459,11 @@ size_t operator_ws_bytes(const tfcb_geometry& g, tfcb_dtype dt) {
   cv.take(sizeof(double) * g.n_views);
   cv.take(sizeof(ViewInfo) * g.n_views);
   cv.take(sizeof(ColInfo) * (size_t)g.n_views * g.nu);
-  cv.take(std::max(nvox(g), npix(g)) * dtype_size(dt));
+  // project: the two padded copies; backproject: the prescaled projections
+  const size_t es = dtype_size(dt);
+  const size_t proj_ws = align_up(pad_elems(g.ny, g.nx, g.nz) * es) +
+                         align_up(pad_elems(g.nx, g.ny, g.nz) * es);
+  cv.take(std::max(proj_ws, npix(g) * es));
   return cv.off;
 }
 

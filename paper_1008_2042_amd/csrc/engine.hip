@@ -69,13 +69,17 @@ tfcb_status tfcb_project(const tfcb_geometry* g, tfcb_dtype dt, const void* vol,
     double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
     ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
     ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
-    T* volT = static_cast<T*>(cv.take(nvox(*g) * sizeof(T)));
+    const size_t nN = pad_elems(g->ny, g->nx, g->nz), nT = pad_elems(g->nx, g->ny, g->nz);
+    T* padN = static_cast<T*>(cv.take(nN * sizeof(T)));
+    T* padT = static_cast<T*>(cv.take(nT * sizeof(T)));
     const double* angd = nullptr;
     TFCB_TRY(upload_angles(*g, ang, s, &angd));
     TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
     const GeomDev gd = make_geom_dev(*g);
-    TFCB_HIP(launch_transpose_xy(g->nx, g->ny, g->nz, static_cast<const T*>(vol), volT, s));
-    TFCB_HIP(launch_project(gd, views, cols, static_cast<const T*>(vol), (const T*)volT, 0,
+    TFCB_HIP(launch_fill(nN, 0.f, padN, s));
+    TFCB_HIP(launch_fill(nT, 0.f, padT, s));
+    TFCB_HIP(launch_pad_copies(g->nx, g->ny, g->nz, static_cast<const T*>(vol), padN, padT, s));
+    TFCB_HIP(launch_project(gd, views, cols, (const T*)padN, (const T*)padT, 0,
                             static_cast<const T*>(nullptr), static_cast<T*>(proj),
                             static_cast<T*>(nullptr), nullptr, nullptr, s));
     return TFCB_OK;
@@ -158,7 +162,7 @@ tfcb_status tfcb_cgls(const tfcb_geometry* g, const tfcb_options* o, void* x, co
     const double* ang = nullptr;
     TFCB_TRY(upload_angles(*g, P.angles, s, &ang));
     TFCB_HIP(launch_cgls_reset(P.sc, s));
-    TFCB_TRY(setup_tables(P.grid[0], ang, s));
+    TFCB_TRY(setup_grid<T>(P.grid[0], ang, s));
     TFCB_TRY(run_cgls<T>(P.grid[0], P.sc, static_cast<T*>(x), static_cast<const T*>(proj),
                          o->cgls_steps, s));
     if (stats) {

@@ -175,7 +175,9 @@ __global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int
           }
           v += corr3(l, col[0], col[1], col[2]);
         }
-        if (positivity) v = fmaxf(v, 0.f);
+        // H: negative voxels to zero; a NaN stays NaN (fmaxf would map it to 0
+        // and hide a failed reconstruction from the non-finite check)
+        if (positivity) v = v < 0.f ? 0.f : v;
         const size_t o = ((size_t)zo * ny + py) * nx + px;
         st(out + o, v);
         if (MOM) {

@@ -12,8 +12,24 @@
 
 namespace tfcb {
 
-// Planes [lo, hi] on which the ray may have a non-zero tap (with one plane of
-// margin; taps outside the grid get zero weight in the loop anyway).
+// The sample of plane p: fractional trans and z indices, evaluated exactly
+// as the backprojector evaluates its weights.
+__device__ __forceinline__ float trans_index(const ColInfo& ci, int p) {
+  return fmaf((float)p, ci.dt, ci.t0);
+}
+__device__ __forceinline__ float z_index(const ColInfo& ci, int p, float vz, float zc) {
+  return fmaf(fmaf((float)p, ci.dtau, ci.tau0), vz, zc);
+}
+__device__ __forceinline__ bool sample_inside(const ColInfo& ci, int p, float vz, float zc,
+                                              int nt, int nz) {
+  const float th = trans_index(ci, p), zh = z_index(ci, p, vz, zc);
+  return th > -1.f && th < (float)nt && zh > -1.f && zh < (float)nz;
+}
+
+// The planes [lo, hi] whose sample has trans index in (-1, nt) and z index
+// in (-1, nz), exactly as the loop evaluates them: both indices are
+// monotone in p, so the set is an interval; a division gives it to within a
+// plane, and the ends are then trimmed by evaluating the samples themselves.
 __device__ __forceinline__ void plane_range(const ColInfo& ci, float vz, float zc, int nt, int nz,
                                             int& lo, int& hi) {
   float a = (float)ci.p_lo, b = (float)ci.p_hi;
@@ -36,13 +52,37 @@ __device__ __forceinline__ void plane_range(const ColInfo& ci, float vz, float z
   }
   lo = (int)a;
   hi = (int)b;
+  while (lo <= hi && !sample_inside(ci, lo, vz, zc, nt, nz)) ++lo;
+  while (hi >= lo && !sample_inside(ci, hi, vz, zc, nt, nz)) --hi;
+}
+
+// One plane sample: bilinear interpolation of the padded copy `vb` (pointer
+// at element (0, 0, 0)), trans stride 1, plane stride ntp, z stride zs.
+template <typename T>
+__device__ __forceinline__ float sample(const T* __restrict__ vb, const ColInfo& ci, int p,
+                                        float vz, float zc, int nt, int nz, int ns, int ntp,
+                                        int zs) {
+  const float th = trans_index(ci, p);
+  const float zh = z_index(ci, p, vz, zc);
+  const float tf = floorf(th), zf = floorf(zh);
+  // inside the plane window these are already in [-1, nt-1] and [-1, nz-1];
+  // the clamps only guarantee in-buffer addresses
+  const int it = min(max((int)tf, -1), nt - 1);
+  const int iz = min(max((int)zf, -1), nz - 1);
+  const float wt = th - tf, wz = zh - zf;
+  const int o = (iz * ns + p) * ntp + it;
+  const float v00 = ld(vb + o), v01 = ld(vb + o + 1);
+  const float v10 = ld(vb + o + zs), v11 = ld(vb + o + zs + 1);
+  const float a = fmaf(wt, v01 - v00, v00);
+  const float b = fmaf(wt, v11 - v10, v10);
+  return fmaf(wz, b - a, a);
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __restrict__ views,
                                                  const ColInfo* __restrict__ cols,
-                                                 const T* __restrict__ vol,
-                                                 const T* __restrict__ volT,
+                                                 const T* __restrict__ padN,
+                                                 const T* __restrict__ padT,
                                                  const T* __restrict__ gin, T* __restrict__ out,
                                                  T* __restrict__ rl, double* __restrict__ partials) {
   __shared__ double red[4];
@@ -54,37 +94,23 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
   if (active) {
     const ViewInfo vi = views[view];
     const ColInfo ci = cols[(size_t)view * g.nu + c];
-    const T* __restrict__ v = vi.step_x ? volT : vol;
     const int nt = vi.step_x ? g.ny : g.nx;
     const int ns = vi.step_x ? g.nx : g.ny;
     const int nz = g.nz;
+    const int ntp = nt + 1, zs = ns * ntp;
+    const T* __restrict__ vb = (vi.step_x ? padT : padN) + pad_index(ns, nt, 0, 0, 0);
     const float vz = ((float)r - 0.5f * (float)(g.nv - 1)) * g.dvdz;
     const float zc = 0.5f * (float)(nz - 1);
     int lo, hi;
     plane_range(ci, vz, zc, nt, nz, lo, hi);
-    float acc = 0.f;
-    for (int p = lo; p <= hi; ++p) {
-      const float fp = (float)p;
-      const float th = fmaf(fp, ci.dt, ci.t0);
-      const float tau = fmaf(fp, ci.dtau, ci.tau0);
-      const float zh = fmaf(tau, vz, zc);
-      const float tf = floorf(th), zf = floorf(zh);
-      const int it = (int)tf, iz = (int)zf;
-      float wt1 = th - tf, wz1 = zh - zf;
-      float wt0 = 1.f - wt1, wz0 = 1.f - wz1;
-      const bool t0ok = (unsigned)it < (unsigned)nt, t1ok = (unsigned)(it + 1) < (unsigned)nt;
-      const bool z0ok = (unsigned)iz < (unsigned)nz, z1ok = (unsigned)(iz + 1) < (unsigned)nz;
-      wt0 = t0ok ? wt0 : 0.f;
-      wt1 = t1ok ? wt1 : 0.f;
-      wz0 = z0ok ? wz0 : 0.f;
-      wz1 = z1ok ? wz1 : 0.f;
-      const int i0 = t0ok ? it : 0, i1 = t1ok ? it + 1 : 0;
-      const int k0 = z0ok ? iz : 0, k1 = z1ok ? iz + 1 : 0;
-      const int b0 = (k0 * ns + p) * nt, b1 = (k1 * ns + p) * nt;
-      const float v00 = ld(v + b0 + i0), v01 = ld(v + b0 + i1);
-      const float v10 = ld(v + b1 + i0), v11 = ld(v + b1 + i1);
-      acc += wz0 * fmaf(wt0, v00, wt1 * v01) + wz1 * fmaf(wt0, v10, wt1 * v11);
+    float acc0 = 0.f, acc1 = 0.f;
+    int p = lo;
+    for (; p < hi; p += 2) {
+      acc0 += sample(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs);
+      acc1 += sample(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs);
     }
+    if (p == hi) acc0 += sample(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs);
+    const float acc = acc0 + acc1;
     const float ell = ray_length(g, vi, ci, r);
     const size_t o = ((size_t)view * g.nv + r) * g.nu + c;
     const float val = ell * acc;
@@ -115,19 +141,19 @@ int project_num_blocks(const GeomDev& g) {
 
 template <typename T>
 hipError_t launch_project(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
-                          const T* vol, const T* volT, int mode, const T* gin, T* out, T* rl,
+                          const T* padN, const T* padT, int mode, const T* gin, T* out, T* rl,
                           double* partials, int* n_partials, hipStream_t s) {
   dim3 block(256);
   dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
   if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
   if (mode == 0)
-    hipLaunchKernelGGL((k_project<T, 0>), grid, block, 0, s, g, views, cols, vol, volT, gin, out,
+    hipLaunchKernelGGL((k_project<T, 0>), grid, block, 0, s, g, views, cols, padN, padT, gin, out,
                        rl, partials);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_project<T, 1>), grid, block, 0, s, g, views, cols, vol, volT, gin, out,
+    hipLaunchKernelGGL((k_project<T, 1>), grid, block, 0, s, g, views, cols, padN, padT, gin, out,
                        rl, partials);
   else
-    hipLaunchKernelGGL((k_project<T, 2>), grid, block, 0, s, g, views, cols, vol, volT, gin, out,
+    hipLaunchKernelGGL((k_project<T, 2>), grid, block, 0, s, g, views, cols, padN, padT, gin, out,
                        rl, partials);
   return hipGetLastError();
 }

@@ -136,7 +136,7 @@ tfcb_status prologue(tfcb_server* S, Request& R) {
   }
   TFCB_HIP(launch_cgls_reset(P.sc, s));
   const int ng = R.opts.n_grids;
-  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_tables(P.grid[l], ang, s));
+  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_grid<T>(P.grid[l], ang, s));
   TFCB_HIP((launch_cast<float, T>(npix(R.geom), R.proj, static_cast<T*>(P.grid[0].g), s)));
   for (int l = 1; l < ng; ++l) {
     const GridBufs& f = P.grid[l - 1];
@@ -208,7 +208,7 @@ tfcb_status advance(tfcb_server* S, Request& R) {
                            R.opts.positivity, static_cast<const T*>(R.xa),
                            static_cast<T*>(R.f_nxt), static_cast<const T*>(R.f_cur),
                            static_cast<T*>(R.xb), (float)R.mom[R.iter + 1],
-                           static_cast<T*>(b.s), static_cast<T*>(b.pT), s));
+                           static_cast<T*>(b.s), static_cast<T*>(b.t2), s));
   std::swap(R.f_cur, R.f_nxt);
   std::swap(R.xa, R.xb);
   R.iter += 1;

@@ -30,6 +30,29 @@ template <> __device__ __forceinline__ void st<__hip_bfloat16>(__hip_bfloat16* p
 
 inline size_t dtype_size(tfcb_dtype dt) { return dt == TFCB_F32 ? 4 : 2; }
 
+// ------------------------------------------------------- padded copies
+// The projector reads a volume through zero-padded copies laid out
+// [nz + 2][ns][nt + 1] (one zero slice below and above in z, one zero column
+// after every trans row) behind one leading zero element.  Element (k, p, i)
+// with k in [-1, nz], p in [0, ns), i in [-1, nt] sits at
+// 1 + ((k + 1) ns + p)(nt + 1) + i, so every bilinear tap of a sample with
+// trans index in (-1, nt) and z index in (-1, nz) is inside the buffer and
+// the taps that fall off the grid read exact zeros: no compares in the loop.
+// "native" copy: ns = ny, nt = nx (y-stepping views); "transposed" copy:
+// ns = nx, nt = ny (x-stepping views).  Only the interior is ever written;
+// the pads are cleared once per call.
+inline size_t pad_elems(int ns, int nt, int nz) {
+  return 1 + (size_t)(nz + 2) * (size_t)ns * (size_t)(nt + 1);
+}
+inline size_t pad_elems_vol(int nx, int ny, int nz) {
+  // the larger of the two copies' sizes (they differ only in nt + 1)
+  const size_t a = pad_elems(ny, nx, nz), b = pad_elems(nx, ny, nz);
+  return a > b ? a : b;
+}
+__host__ __device__ __forceinline__ int pad_index(int ns, int nt, int k, int p, int i) {
+  return 1 + ((k + 1) * ns + p) * (nt + 1) + i;
+}
+
 // ------------------------------------------------------------- geometry
 // A view is processed in its own frame: "step" is the axis whose voxel-centre
 // planes the rays cross (x or y), "trans" the other in-plane axis.  For
@@ -50,12 +73,13 @@ struct ViewInfo {
 // at fractional trans index t_p = t0 + p * dt.  The fractional z index of
 // row r is tau_p * vz_r + (nz - 1) / 2 with vz_r = (r - (nv-1)/2) dv / dz.
 // The path length between planes is l = d_step * sqrt(a2 + v_r^2) * inv_astep.
-struct ColInfo {
+struct alignas(16) ColInfo {
   float t0, dt;
   float tau0, dtau;
   float a2, inv_astep;
   int32_t p_lo, p_hi;
 };
+static_assert(sizeof(ColInfo) == 32, "ColInfo is read as two 16-byte vectors");
 
 struct GeomDev {
   int32_t nx, ny, nz, nu, nv, n_views;
@@ -124,12 +148,17 @@ __device__ __forceinline__ float ray_length(const GeomDev& g, const ViewInfo& vi
 hipError_t launch_geom_tables(const tfcb_geometry& g, const double* angles_dev, ViewInfo* views,
                               ColInfo* cols, hipStream_t s);
 
-// P.  mode 0: out = P vol.  mode 1: r = g - P vol, rl = l * r, partial ||r||^2.
-//     mode 2: out = P vol, partial ||out||^2.
+// P of a volume given as its two zero-padded copies (padN native, padT
+// transposed).  mode 0: out = P vol.  mode 1: r = g - P vol, rl = l * r,
+// partial ||r||^2.  mode 2: out = P vol, partial ||out||^2.
 template <typename T>
 hipError_t launch_project(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
-                          const T* vol, const T* volT, int mode, const T* gin, T* out, T* rl,
+                          const T* padN, const T* padT, int mode, const T* gin, T* out, T* rl,
                           double* partials, int* n_partials, hipStream_t s);
+// Interior of both padded copies from a native [z][y][x] volume.
+template <typename T>
+hipError_t launch_pad_copies(int nx, int ny, int nz, const T* in, T* padN, T* padT,
+                             hipStream_t s);
 int project_num_blocks(const GeomDev& g);
 
 // P^T of the length-prescaled projections rl (= l * g).  Writes vol and,
@@ -170,11 +199,12 @@ template <typename T>
 hipError_t launch_residual_update(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
                                   T* r, const T* q, T* rl, const CglsScalars* sc,
                                   double* partials, int* n_partials, hipStream_t s);
-// Normalised direction pn (see CglsScalars).  mode 0: pn = s / sigma (s may
-// alias p) and pT.  mode 1: x += alpha pn; pn = (s + beta_sigma pn) / sigma'
-// and pT.  mode 2: x += alpha pn only.
+// Normalised direction pn (see CglsScalars), kept only as its two padded
+// copies pN (native) and pT (transposed).  mode 0: pn = s / sigma.
+// mode 1: x += alpha pn; pn = (s + beta_sigma pn) / sigma'.  mode 2:
+// x += alpha pn only.
 template <typename T>
-hipError_t launch_xp_update(int nx, int ny, int nz, int mode, T* x, T* p, T* pT, const T* s,
+hipError_t launch_xp_update(int nx, int ny, int nz, int mode, T* x, T* pN, T* pT, const T* s,
                             const CglsScalars* sc, hipStream_t s_);
 hipError_t launch_cgls_reset(CglsScalars* sc, hipStream_t s);
 

@@ -97,7 +97,8 @@ hipError_t launch_cgls_reset(CglsScalars* sc, hipStream_t s) {
 // written with full rows.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_xp_update(int nx, int ny, T* __restrict__ x,
-                                                   T* p, T* __restrict__ pT, const T* s,
+                                                   T* __restrict__ pN, T* __restrict__ pT,
+                                                   const T* __restrict__ s,
                                                    const CglsScalars* __restrict__ sc) {
   __shared__ float tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -111,17 +112,18 @@ __global__ __launch_bounds__(256) void k_xp_update(int nx, int ny, T* __restrict
     const int yy = y0 + ty + 8 * rr, xx = x0 + tx;
     if (xx < nx && yy < ny) {
       const size_t o = zoff + (size_t)yy * nx + xx;
+      const int on = pad_index(ny, nx, z, yy, xx);
       float pn;
       if (MODE == 0) {
         pn = ld(s + o) * inv_sigma;
       } else {
-        const float pv = ld(p + o);
+        const float pv = ld(pN + on);
         if (!stopped) st(x + o, fmaf(alpha, pv, ld(x + o)));
         pn = (MODE == 1) ? fmaf(beta_sigma, pv, ld(s + o)) * inv_sigma : pv;
       }
       if (MODE != 2) {
-        st(p + o, pn);
-        tile[ty + 8 * rr][tx] = ld(p + o);
+        st(pN + on, pn);
+        tile[ty + 8 * rr][tx] = ld(pN + on);
       }
     }
   }
@@ -130,8 +132,41 @@ __global__ __launch_bounds__(256) void k_xp_update(int nx, int ny, T* __restrict
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int xx = x0 + ty + 8 * rr, yy = y0 + tx;
-    if (xx < nx && yy < ny) st(pT + zoff + (size_t)xx * ny + yy, tile[tx][ty + 8 * rr]);
+    if (xx < nx && yy < ny) st(pT + pad_index(nx, ny, z, xx, yy), tile[tx][ty + 8 * rr]);
   }
+}
+
+// Interior of the padded native and transposed copies of a native volume.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_copies(int nx, int ny, const T* __restrict__ in,
+                                                    T* __restrict__ padN, T* __restrict__ padT) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+  const size_t zoff = (size_t)z * nx * ny;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int yy = y0 + ty + 8 * rr, xx = x0 + tx;
+    if (xx < nx && yy < ny) {
+      const float v = ld(in + zoff + (size_t)yy * nx + xx);
+      st(padN + pad_index(ny, nx, z, yy, xx), v);
+      tile[ty + 8 * rr][tx] = v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int xx = x0 + ty + 8 * rr, yy = y0 + tx;
+    if (xx < nx && yy < ny) st(padT + pad_index(nx, ny, z, xx, yy), tile[tx][ty + 8 * rr]);
+  }
+}
+
+template <typename T>
+hipError_t launch_pad_copies(int nx, int ny, int nz, const T* in, T* padN, T* padT,
+                             hipStream_t s) {
+  dim3 grid((nx + 31) / 32, (ny + 31) / 32, nz);
+  hipLaunchKernelGGL((k_pad_copies<T>), grid, dim3(256), 0, s, nx, ny, in, padN, padT);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -331,6 +366,7 @@ hipError_t launch_prolong(const tfcb_geometry& co, const tfcb_geometry& fi, cons
   template hipError_t launch_xp_update<T>(int, int, int, int, T*, T*, T*, const T*,             \
                                           const CglsScalars*, hipStream_t);                    \
   template hipError_t launch_transpose_xy<T>(int, int, int, const T*, T*, hipStream_t);          \
+  template hipError_t launch_pad_copies<T>(int, int, int, const T*, T*, T*, hipStream_t);         \
   template hipError_t launch_copy<T>(size_t, const T*, T*, hipStream_t);                        \
   template hipError_t launch_fill<T>(size_t, float, T*, hipStream_t);                           \
   template hipError_t launch_nonfinite<T>(size_t, const T*, int*, hipStream_t);                 \
