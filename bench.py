@@ -127,7 +127,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f16", action="store_true", help="skip the FP16-storage companion run")
+    ap.add_argument("--no-f16", action="store_true", help="skip the FP16/BF16-storage runs")
+    ap.add_argument("--serving", type=int, default=16, metavar="N",
+                    help="requests in the serving measurement (0 = skip; 64 = the full mix)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -223,13 +225,17 @@ def main():
         "roofline": roofline,
     }
     if not args.no_f16:
-        vol16, dt16, _ = run(tfcb.F16, args.steps, 1, False)
-        a = vol16.double()
-        b = vol32.double()
-        line["config"]["f16_storage"] = {
-            "value": round(n_iters * args.steps / dt16, 3), "unit": "TF iterations/s",
-            "ms_per_step": round(dt16 / args.steps * 1e3, 3),
-            "rel_l2_vs_f32": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
+        for name, code in (("f16_storage", tfcb.F16), ("bf16_storage", tfcb.BF16)):
+            volh, dth, _ = run(code, args.steps, 1, False)
+            a = volh.double()
+            b = vol32.double()
+            line["config"][name] = {
+                "value": round(n_iters * args.steps / dth, 3), "unit": "TF iterations/s",
+                "ms_per_step": round(dth / args.steps * 1e3, 3),
+                "rel_l2_vs_f32": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
+    if args.serving > 0:
+        from paper_1008_2042_amd import serve
+        line["config"]["serving"] = serve.serving_benchmark(n=args.serving, device=dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, y)
     print(json.dumps(line), flush=True)
