@@ -130,6 +130,9 @@ def main():
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--serving", type=int, default=16, metavar="N",
                     help="requests in the serving measurement (0 = skip; 64 = the full mix)")
+    ap.add_argument("--workload", default="paper", choices=["paper", "large"],
+                    help="paper: 512x512x70, 40 views (default); large: 512x512x256, "
+                         "360 views of 1024x768, 3 grids, 2-level framelet")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,10 +151,26 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     tfcb.load()
-    cfg = inputs.config("paper")
+    cfg = inputs.config(args.workload)
     g = cfg["geom"]
-    y = inputs.measured_data(cfg)
-    yd = torch.tensor(y, dtype=torch.float32, device=dev)
+    if args.workload == "paper":
+        y = inputs.measured_data(cfg)
+        yd = torch.tensor(y, dtype=torch.float32, device=dev)
+        workload = ("paper-scale TF reconstruction: 512x512x70 volume at 0.5x0.5x2.5 mm, 40 "
+                    "views, 512x384 detector at 0.776 mm, 2-grid multigrid 16+24 iterations, "
+                    "3 CGLS steps, 1-level framelet, lambda 5e-4, 20-ellipsoid phantom, "
+                    "Poisson I0=1e5")
+    else:
+        # 283 M rays: the chords are evaluated on the device (FP64), then Poisson noise
+        clean = inputs.analytic_projection_torch(g, inputs.phantom_for(cfg), dev)
+        yd = inputs.poisson_log_torch(clean, cfg["noise"][0], cfg["noise"][1]).float()
+        del clean
+        y = None
+        args.no_cpu_baseline = True
+        workload = ("large single TF reconstruction: 512x512x256 volume at 0.5 mm, 360 views, "
+                    "1024x768 detector at 0.388 mm, 3-grid multigrid 5+10+15 iterations, "
+                    "3 CGLS steps, 2-level framelet, lambda 5e-4, 40-ellipsoid phantom, "
+                    "Poisson I0=5e4")
     n_iters = sum(cfg["iters"])
 
     def run(storage, steps, warmup, profile):
@@ -206,14 +225,11 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "paper-scale TF reconstruction: 512x512x70 volume at "
-                               "0.5x0.5x2.5 mm, 40 views, 512x384 detector at 0.776 mm, "
-                               "2-grid multigrid 16+24 iterations, 3 CGLS steps, 1-level "
-                               "framelet, lambda 5e-4, 20-ellipsoid phantom, Poisson I0=1e5",
+        "config": {"workload": workload,
                    "s_per_recon": round(ms_per_step / 1e3, 4),
                    "iterations_per_recon": n_iters,
-                   "fine_grid_iters_per_s": round(cfg["iters"][1] / np.mean(
-                       [r["seconds_per_grid"][1] for r in reps]), 3),
+                   "fine_grid_iters_per_s": round(cfg["iters"][-1] / np.mean(
+                       [r["seconds_per_grid"][len(cfg["iters"]) - 1] for r in reps]), 3),
                    "coarse_grid_iters_per_s": round(cfg["iters"][0] / np.mean(
                        [r["seconds_per_grid"][0] for r in reps]), 3),
                    "kernel_avg_ms": {KERNEL_NAMES[i]: round(avg_ms[i], 4) for i in range(3)},
@@ -233,7 +249,7 @@ def main():
                 "value": round(n_iters * args.steps / dth, 3), "unit": "TF iterations/s",
                 "ms_per_step": round(dth / args.steps * 1e3, 3),
                 "rel_l2_vs_f32": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
-    if args.serving > 0:
+    if args.serving > 0 and args.workload == "paper":
         from paper_1008_2042_amd import serve
         line["config"]["serving"] = serve.serving_benchmark(n=args.serving, device=dev)
     if not args.no_cpu_baseline:

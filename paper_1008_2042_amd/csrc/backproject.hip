@@ -1,31 +1,33 @@
 // Backprojector P^T: the exact transpose of the Joseph projector, evaluated
-// as a gather, one thread per voxel, no atomics (the paper's section 2.2.2
-// motivates a voxel-driven P^T by the write conflicts of a ray-driven one;
-// here the voxel-driven form is the exact matrix transpose rather than the
-// continuous closed form of Eq. (3)).
+// as a gather, one thread per voxel run, no atomics (the paper's section
+// 2.2.2 motivates a voxel-driven P^T by the write conflicts of a ray-driven
+// one; here the voxel-driven form is the exact matrix transpose rather than
+// the continuous closed form of Eq. (3)).
 //
 // For voxel (i, j, k) and a view stepping along axis s, the voxel lies on
 // plane p (its index along s) at trans index t.  Ray (c, r) weights it by
-// l(c,r) * hat(t_p(c) - t) * hat(z_p(c,r) - k), the same FP32 expressions
-// (same table entries, same operation order) as the projector.  The columns
+// l(c,r) * hat(t_p(c) - t) * hat(z_p(c,r) - k), with the projector's FP32
+// expressions for t_p and z_p (same table entries, same FMAs).  The columns
 // with hat(t_p(c) - t) > 0 are those whose detector coordinate lies between
 // the projections of the trans neighbours t - 1 and t + 1 on plane p; for
-// each such column the rows follow from |tau_p(c) vz_r + zc - k| < 1.  The
+// each such column the rows follow from the z index of the row.  The
 // projections are prescaled by l (rl = l * g) once per application.
 //
-// Mapping: 256-thread blocks of 64 (x) x 4 (y) voxels of one z slice.  For a
-// y-stepping view the lanes of a wavefront read adjacent detector columns;
-// for an x-stepping view they sit on adjacent planes and read nearly the
-// same (column, row) footprint.  Both are served by one or two cache lines
-// per tap.
+// Mapping: 256-thread blocks of 64 (x) x 4 (y) voxel columns; each thread
+// accumulates a run of K voxels along z.  Per view the block first stages
+// its whole detector footprint (the bounding box of the projection of its
+// voxel box grown by one voxel, the support of the hat weights) into LDS
+// with coalesced row loads, so every tap is an LDS read; a view whose
+// footprint does not fit the tile is read from global memory instead.
+// Within a column the footprint rows are split into z segments (rows whose
+// z index lies between two voxel centres): each row is read once, and the
+// segment sums of g and fr * g give both tent weights.
 #include "tfcb_internal.h"
 
 namespace tfcb {
 
-// Voxels per thread along z: one thread accumulates K consecutive voxels of
-// an (x, y) column, sharing the per-view and per-column work, and loads each
-// detector row of a column's footprint once.
-constexpr int kZRun = 8;
+constexpr int kZRun = 8;     // voxels per thread along z
+constexpr int kTile = 6144;  // LDS floats for one view's staged footprint (24 KB)
 
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
@@ -34,86 +36,127 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
                                                      T* __restrict__ vol,
                                                      double* __restrict__ partials) {
   __shared__ double red[4];
+  __shared__ float tile[kTile];
+  __shared__ float cbox[2][8];  // projected corner columns / rows
   extern __shared__ float vz_tab[];  // vz_r = (r - (nv-1)/2) dv/dz, as the projector forms it
   const float rc = 0.5f * (float)(g.nv - 1);
   for (int r = threadIdx.x; r < g.nv; r += blockDim.x) vz_tab[r] = ((float)r - rc) * g.dvdz;
-  __syncthreads();
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int j = blockIdx.y * 4 + wave;
   const int k0 = blockIdx.z * K;
   const bool active = i < g.nx && j < g.ny;
-  double part = 0.0;
-  if (active) {
-    const float xc = 0.5f * (float)(g.nx - 1), yc = 0.5f * (float)(g.ny - 1);
-    const float zc = 0.5f * (float)(g.nz - 1);
-    const float cu = 0.5f * (float)(g.nu - 1);
-    const float inv_du = 1.f / g.du;
-    const float X = ((float)i - xc) * g.dx, Y = ((float)j - yc) * g.dy;
-    float acc[K];
+  const float xc = 0.5f * (float)(g.nx - 1), yc = 0.5f * (float)(g.ny - 1);
+  const float zc = 0.5f * (float)(g.nz - 1);
+  const float cu = 0.5f * (float)(g.nu - 1);
+  const float inv_du = 1.f / g.du, inv_dv = 1.f / g.dv;
+  const float X = ((float)i - xc) * g.dx, Y = ((float)j - yc) * g.dy;
+  // the block's voxel box grown by one voxel on every side (mm)
+  const float bx0 = ((float)(blockIdx.x * 64 - 1) - xc) * g.dx;
+  const float bx1 = ((float)(min(g.nx, (int)blockIdx.x * 64 + 64)) - xc) * g.dx;
+  const float by0 = ((float)(blockIdx.y * 4 - 1) - yc) * g.dy;
+  const float by1 = ((float)(min(g.ny, (int)blockIdx.y * 4 + 4)) - yc) * g.dy;
+  const float bz0 = ((float)(k0 - 1) - zc) * g.dz;
+  const float bz1 = ((float)(min(g.nz, k0 + K)) - zc) * g.dz;
+
+  float acc[K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = 0.f;
-    for (int view = 0; view < g.n_views; ++view) {
-      const ViewInfo vi = views[view];
-      int p, t;
-      float Xa, Ya, Xb, Yb;  // the trans neighbours t - 1 and t + 1 on plane p
-      if (vi.step_x) {
-        p = i;
-        t = j;
-        Xa = X; Xb = X;
-        Ya = Y - g.dy; Yb = Y + g.dy;
-      } else {
-        p = j;
-        t = i;
-        Ya = Y; Yb = Y;
-        Xa = X - g.dx; Xb = X + g.dx;
+  for (int q = 0; q < K; ++q) acc[q] = 0.f;
+
+  for (int view = 0; view < g.n_views; ++view) {
+    const ViewInfo vi = views[view];
+    const T* __restrict__ rview = rl + (size_t)view * g.nv * g.nu;
+    // ---- footprint box: project the 8 corners of the grown voxel box
+    __syncthreads();  // previous view's tile reads are done
+    if (threadIdx.x < 8) {
+      const float cx = (threadIdx.x & 1) ? bx1 : bx0;
+      const float cy = (threadIdx.x & 2) ? by1 : by0;
+      const float cz = (threadIdx.x & 4) ? bz1 : bz0;
+      const float den = __builtin_amdgcn_rcpf(g.sad - (cx * vi.cs + cy * vi.sn));
+      cbox[0][threadIdx.x] = fmaf(g.sdd * (-cx * vi.sn + cy * vi.cs) * den, inv_du, cu);
+      cbox[1][threadIdx.x] = fmaf(g.sdd * cz * den, inv_dv, rc);
+    }
+    __syncthreads();
+    float umin = cbox[0][0], umax = umin, vmin = cbox[1][0], vmax = vmin;
+#pragma unroll
+    for (int e = 1; e < 8; ++e) {
+      umin = fminf(umin, cbox[0][e]);
+      umax = fmaxf(umax, cbox[0][e]);
+      vmin = fminf(vmin, cbox[1][e]);
+      vmax = fmaxf(vmax, cbox[1][e]);
+    }
+    const int c0 = max(0, (int)floorf(umin) - 1), c1 = min(g.nu - 1, (int)ceilf(umax) + 1);
+    const int r0 = max(0, (int)floorf(vmin) - 1), r1 = min(g.nv - 1, (int)ceilf(vmax) + 1);
+    const int W = c1 - c0 + 1, H = r1 - r0 + 1;
+    const bool staged = W > 0 && H > 0 && W * H <= kTile;
+    if (staged) {
+      for (int rr = wave; rr < H; rr += 4) {
+        const T* src = rview + (size_t)(r0 + rr) * g.nu + c0;
+        for (int cc = lane; cc < W; cc += 64) tile[rr * W + cc] = ld(src + cc);
       }
-      // detector column of a point: u = sdd (-x sn + y cs) / (sad - (x cs + y sn));
-      // the columns are only bracketed here (one column of slack each side),
-      // so the hardware reciprocal is accurate enough
-      const float ua = g.sdd * (-Xa * vi.sn + Ya * vi.cs) *
-                       __builtin_amdgcn_rcpf(g.sad - (Xa * vi.cs + Ya * vi.sn));
-      const float ub = g.sdd * (-Xb * vi.sn + Yb * vi.cs) *
-                       __builtin_amdgcn_rcpf(g.sad - (Xb * vi.cs + Yb * vi.sn));
-      const float ca = fmaf(ua, inv_du, cu), cb = fmaf(ub, inv_du, cu);
-      const int clo = max(0, (int)floorf(fminf(ca, cb)));
-      const int chi = min(g.nu - 1, (int)ceilf(fmaxf(ca, cb)));
-      const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
-      const T* __restrict__ rview = rl + (size_t)view * g.nv * g.nu;
-      const float fp = (float)p;
-      for (int c = clo; c <= chi; ++c) {
-        // both halves of the 32-byte record in two vector loads, issued together
-        const float4 h0 = reinterpret_cast<const float4*>(cview + c)[0];
-        const int4 h1 = reinterpret_cast<const int4*>(cview + c)[1];
-        ColInfo ci;
-        ci.t0 = h0.x;
-        ci.dt = h0.y;
-        ci.tau0 = h0.z;
-        ci.dtau = h0.w;
-        ci.p_lo = h1.z;
-        ci.p_hi = h1.w;
-        if (p < ci.p_lo || p > ci.p_hi) continue;
-        const float th = fmaf(fp, ci.dt, ci.t0);
-        const float wt = 1.f - fabsf(th - (float)t);
-        if (wt <= 0.f) continue;
-        const float tau = fmaf(fp, ci.dtau, ci.tau0);
-        // The z index of row r is zh_r = tau vz_r + zc (increasing in r).
-        // Segment m = the rows with floor(zh_r) = k0 - 1 + m, m = 0..K: its
-        // rows give (1 - fr) of their value to voxel k0 - 1 + m and fr to
-        // voxel k0 + m, fr = zh_r - (k0 - 1 + m).  Segment bounds come from
-        // the inverse of the row map; a row misplaced by rounding at a bound
-        // has fr within an ulp of 0 or 1, so its weights are still right.
-        const float inv_s = __builtin_amdgcn_rcpf(tau * g.dvdz);
-        const T* __restrict__ colp = rview + c;
-        float s0[K + 1], s1[K + 1];
-        int rb = min(g.nv, max(0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
+    }
+    __syncthreads();
+    if (!active || W <= 0 || H <= 0) continue;
+
+    int p, t;
+    float Xa, Ya, Xb, Yb;  // the trans neighbours t - 1 and t + 1 on plane p
+    if (vi.step_x) {
+      p = i;
+      t = j;
+      Xa = X;
+      Xb = X;
+      Ya = Y - g.dy;
+      Yb = Y + g.dy;
+    } else {
+      p = j;
+      t = i;
+      Ya = Y;
+      Yb = Y;
+      Xa = X - g.dx;
+      Xb = X + g.dx;
+    }
+    // detector column of a point: u = sdd (-x sn + y cs) / (sad - (x cs + y sn));
+    // the columns are only bracketed (one column of slack each side), so the
+    // hardware reciprocal is accurate enough
+    const float ua = g.sdd * (-Xa * vi.sn + Ya * vi.cs) *
+                     __builtin_amdgcn_rcpf(g.sad - (Xa * vi.cs + Ya * vi.sn));
+    const float ub = g.sdd * (-Xb * vi.sn + Yb * vi.cs) *
+                     __builtin_amdgcn_rcpf(g.sad - (Xb * vi.cs + Yb * vi.sn));
+    const float ca = fmaf(ua, inv_du, cu), cb = fmaf(ub, inv_du, cu);
+    // every column with a non-zero weight lies inside the footprint box
+    const int clo = max(c0, (int)floorf(fminf(ca, cb)));
+    const int chi = min(c1, (int)ceilf(fmaxf(ca, cb)));
+    const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
+    const float fp = (float)p;
+    for (int c = clo; c <= chi; ++c) {
+      // both halves of the 32-byte record in two vector loads, issued together
+      const float4 h0 = reinterpret_cast<const float4*>(cview + c)[0];
+      const int4 h1 = reinterpret_cast<const int4*>(cview + c)[1];
+      if (p < h1.z || p > h1.w) continue;  // plane outside 0 < tau < 1
+      const float th = fmaf(fp, h0.y, h0.x);
+      const float wt = 1.f - fabsf(th - (float)t);
+      if (wt <= 0.f) continue;
+      const float tau = fmaf(fp, h0.w, h0.z);
+      // The z index of row r is zh_r = tau vz_r + zc (increasing in r).
+      // Segment m = the rows with floor(zh_r) = k0 - 1 + m, m = 0..K: its
+      // rows give (1 - fr) of their value to voxel k0 - 1 + m and fr to
+      // voxel k0 + m, fr = zh_r - (k0 - 1 + m).  Segment bounds come from
+      // the inverse of the row map; a row misplaced by rounding at a bound
+      // has fr within an ulp of 0 or 1, so its weights are still right.
+      const float inv_s = __builtin_amdgcn_rcpf(tau * g.dvdz);
+      float s0[K + 1], s1[K + 1];
+      int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
+      if (staged) {
+        const int tc = c - c0;  // tile column; tile row = r - r0
 #pragma unroll
         for (int m = 0; m <= K; ++m) {
           const float base = (float)(k0 - 1 + m);
-          const int re = min(g.nv, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
+          const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
           float a0 = 0.f, a1 = 0.f;
           for (int r = rb; r < re; ++r) {
             const float fr = fmaf(tau, vz_tab[r], zc) - base;
-            const float gv = ld(colp + r * g.nu);
+            const float gv = tile[(r - r0) * W + tc];
             a0 += gv;
             a1 = fmaf(fr, gv, a1);
           }
@@ -121,10 +164,31 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
           s1[m] = a1;
           rb = re;
         }
+      } else {
+        const T* __restrict__ colp = rview + c;
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = fmaf(wt, s1[q] + (s0[q + 1] - s1[q + 1]), acc[q]);
+        for (int m = 0; m <= K; ++m) {
+          const float base = (float)(k0 - 1 + m);
+          const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
+          float a0 = 0.f, a1 = 0.f;
+          for (int r = rb; r < re; ++r) {
+            const float fr = fmaf(tau, vz_tab[r], zc) - base;
+            const float gv = ld(colp + (size_t)r * g.nu);
+            a0 += gv;
+            a1 = fmaf(fr, gv, a1);
+          }
+          s0[m] = a0;
+          s1[m] = a1;
+          rb = re;
+        }
       }
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] = fmaf(wt, s1[q] + (s0[q + 1] - s1[q + 1]), acc[q]);
     }
+  }
+
+  double part = 0.0;
+  if (active) {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       if (k0 + q < g.nz) {

@@ -61,7 +61,9 @@ tfcb_status validate_geometry(const tfcb_geometry* g) {
     return fail(TFCB_EINVAL, "voxel and pixel sizes must be finite and > 0");
   if (!finite_pos(g->sad) || !std::isfinite(g->sdd) || !(g->sdd > g->sad))
     return fail(TFCB_EINVAL, "need 0 < sad < sdd (sad=%g sdd=%g)", g->sad, g->sdd);
-  const double hx = 0.5 * g->nx * g->dx, hy = 0.5 * g->ny * g->dy;
+  // the volume grown by two voxels (the backprojector's footprint boxes)
+  // must stay inside the source orbit
+  const double hx = (0.5 * g->nx + 2.0) * g->dx, hy = (0.5 * g->ny + 2.0) * g->dy;
   if (!(std::sqrt(hx * hx + hy * hy) < g->sad))
     return fail(TFCB_EINVAL, "the volume must lie inside the source orbit (half-diagonal %g >= sad %g)",
                 std::sqrt(hx * hx + hy * hy), g->sad);

@@ -215,9 +215,22 @@ def analytic_projection(g: Geometry, ellipsoids: List[Ellipsoid]) -> np.ndarray:
     return out
 
 
-def analytic_projection_torch(g: Geometry, ellipsoids: List[Ellipsoid], device):
+def analytic_projection_torch(g: Geometry, ellipsoids: List[Ellipsoid], device,
+                              views_per_chunk: int = 40):
     """The same exact chord integrals as analytic_projection, evaluated in
-    FP64 with torch on `device` (fast generation of large serving mixes)."""
+    FP64 with torch on `device` (fast generation of large serving mixes),
+    a chunk of views at a time."""
+    import torch
+    out = torch.empty((g.n_views, g.nv, g.nu), dtype=torch.float64, device=device)
+    ang = g.view_angles()
+    for v0 in range(0, g.n_views, views_per_chunk):
+        v1 = min(g.n_views, v0 + views_per_chunk)
+        sub = dataclasses.replace(g, n_views=v1 - v0, angles=ang[v0:v1])
+        out[v0:v1] = _chords_torch(sub, ellipsoids, device)
+    return out
+
+
+def _chords_torch(g: Geometry, ellipsoids: List[Ellipsoid], device):
     import torch
     f64 = torch.float64
     th = torch.tensor(g.view_angles(), dtype=f64, device=device)

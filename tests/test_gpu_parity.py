@@ -76,6 +76,17 @@ def test_backproject_parity(g):
     assert rel(got, want) <= 1e-4
 
 
+def test_backproject_parity_large_footprint():
+    """A detector 7x finer than the voxels: a block's footprint exceeds the
+    LDS tile, so the backprojector reads the projections from global memory."""
+    dev = _dev()
+    g = Geometry(40, 24, 12, 1.0, 1.0, 1.0, 420, 120, 0.2, 0.2, sad=200.0, sdd=300.0, n_views=4)
+    y = inputs.random_sino(g, 19)
+    announce("backproject large footprint")
+    got = host(tfcb.backproject(g, t32(y, dev)))
+    assert rel(got, oracle.backproject(g, y)) <= 1e-4
+
+
 def test_adjoint_identity_gpu():
     dev = _dev()
     g = RAGGED
