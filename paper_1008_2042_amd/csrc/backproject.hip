@@ -52,11 +52,13 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
   const float cu = 0.5f * (float)(g.nu - 1);
   const float inv_du = 1.f / g.du, inv_dv = 1.f / g.dv;
   const float X = ((float)i - xc) * g.dx, Y = ((float)j - yc) * g.dy;
-  // the block's voxel box grown by one voxel on every side (mm)
-  const float bx0 = ((float)(blockIdx.x * 64 - 1) - xc) * g.dx;
-  const float bx1 = ((float)(min(g.nx, (int)blockIdx.x * 64 + 64)) - xc) * g.dx;
-  const float by0 = ((float)(blockIdx.y * 4 - 1) - yc) * g.dy;
-  const float by1 = ((float)(min(g.ny, (int)blockIdx.y * 4 + 4)) - yc) * g.dy;
+  // the block's voxel box grown by one voxel on every side (mm); signed
+  // arithmetic: the first block's lower bound is index -1
+  const int bi = (int)blockIdx.x * 64, bj = (int)blockIdx.y * 4;
+  const float bx0 = ((float)(bi - 1) - xc) * g.dx;
+  const float bx1 = ((float)min(g.nx, bi + 64) - xc) * g.dx;
+  const float by0 = ((float)(bj - 1) - yc) * g.dy;
+  const float by1 = ((float)min(g.ny, bj + 4) - yc) * g.dy;
   const float bz0 = ((float)(k0 - 1) - zc) * g.dz;
   const float bz1 = ((float)(min(g.nz, k0 + K)) - zc) * g.dz;
 
