@@ -1,0 +1,68 @@
+"""The large single-reconstruction workload (512x512x256 at 0.5 mm, 360 views
+of a 1024x768 detector at 0.388 mm) at its real shape: sampled projector
+outputs against the oracle, the adjoint identity of the full-size operators,
+and a shortened 3-grid, 2-level-framelet reconstruction."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1008_2042_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1008_2042_amd import tfcb  # noqa: E402
+
+LARGE = inputs.config("large")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def announce(msg):
+    print("[gpu-case]", msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_large_project_sampled_and_adjoint():
+    dev = _dev()
+    g = LARGE["geom"]
+    f = inputs.random_volume(g, 41)
+    announce("large project")
+    fd = torch.tensor(f, dtype=torch.float32, device=dev)
+    pf = tfcb.project(g, fd)
+    rng = np.random.default_rng(42)
+    vrc = np.stack([rng.integers(0, g.n_views, 128), rng.integers(0, g.nv, 128),
+                    rng.integers(0, g.nu, 128)], axis=1)
+    got = pf[vrc[:, 0], vrc[:, 1], vrc[:, 2]].double().cpu().numpy()
+    want = oracle.project_rays(g, f, vrc)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-4
+    announce("large adjoint identity")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(43)
+    y = torch.rand(g.sino_shape, generator=gen, device=dev, dtype=torch.float32) * 2 - 1
+    pty = tfcb.backproject(g, y)
+    lhs = float(torch.sum(pf.double() * y.double()))
+    rhs = float(torch.sum(fd.double() * pty.double()))
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
+
+
+@pytest.mark.parametrize("storage", [tfcb.F32, tfcb.F16])
+def test_large_reconstruction_shortened(storage):
+    """Three grids and two framelet levels, one iteration per grid."""
+    dev = _dev()
+    g = LARGE["geom"]
+    announce("large reconstruct storage=%d" % storage)
+    ells = inputs.phantom_for(LARGE)
+    y = inputs.analytic_projection_torch(g, ells, dev).float()
+    vol, rep = tfcb.reconstruct(g, y, LARGE["lam"], [1, 1, 1], framelet_levels=2,
+                                storage=storage)
+    v = vol.cpu().numpy()
+    assert np.all(np.isfinite(v)) and v.min() >= 0.0
+    assert rep["iters_done"] == [1, 1, 1]
+    assert rep["resid2_last"] < 0.5 * float(torch.sum(y.double() ** 2))
