@@ -49,7 +49,8 @@ class OrcOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("n_grids", ctypes.c_int32),
                 ("iters", ctypes.c_int32 * 4), ("cgls_steps", ctypes.c_int32),
                 ("framelet_levels", ctypes.c_int32), ("momentum", ctypes.c_int32),
-                ("positivity", ctypes.c_int32), ("bin_coarse_detector", ctypes.c_int32)]
+                ("positivity", ctypes.c_int32), ("bin_coarse_detector", ctypes.c_int32),
+                ("op_pair", ctypes.c_int32)]
 
 
 class OrcReport(ctypes.Structure):
@@ -77,11 +78,17 @@ def _load():
             "orc_project_rays": ([G, _D, i64, _I, _D], None),
             "orc_backproject": ([G, _D, _D], None),
             "orc_backproject_voxels": ([G, _D, i64, _I, _D], None),
+            "orc_project_siddon": ([G, _D, _D], None),
+            "orc_project_siddon_rays": ([G, _D, i64, _I, _D], None),
+            "orc_backproject_eq3": ([G, _D, _D], None),
+            "orc_backproject_eq3_voxels": ([G, _D, i64, _I, _D], None),
             "orc_framelet_analysis": ([i32, i32, i32, i32, _D, _D], None),
             "orc_framelet_synthesis": ([i32, i32, i32, i32, _D, _D], None),
             "orc_shrink": ([i64, dbl, _D], None),
             "orc_framelet_shrink": ([i32, i32, i32, i32, dbl, i32, _D, _D], None),
             "orc_cgls": ([G, _D, _D, i32, ctypes.POINTER(dbl), ctypes.c_void_p], ctypes.c_int),
+            "orc_cgls_pair": ([G, i32, _D, _D, i32, ctypes.POINTER(dbl), ctypes.c_void_p],
+                              ctypes.c_int),
             "orc_coarse_geom": ([G, i32, G], None),
             "orc_restrict_sino": ([G, _D, _D], None),
             "orc_prolong_vol": ([G, G, _D, _D], None),
@@ -165,6 +172,43 @@ def backproject_voxels(g, proj, kji):
     return out
 
 
+def project_siddon(g, f):
+    """P f by Siddon's method (section 2.2.1): the exact length of each
+    source-to-pixel segment inside each voxel box, times the voxel value."""
+    f = _f64(f, _vol_shape(g))
+    out = np.empty(_sino_shape(g), np.float64)
+    _load().orc_project_siddon(ctypes.byref(_geom(g)), f, out)
+    return out
+
+
+def project_siddon_rays(g, f, vrc):
+    """``project_siddon`` on the listed rays only; vrc is (n, 3) int (view, row, col)."""
+    f = _f64(f, _vol_shape(g))
+    vrc = np.ascontiguousarray(vrc, dtype=np.int32).reshape(-1, 3)
+    out = np.empty(vrc.shape[0], np.float64)
+    _load().orc_project_siddon_rays(ctypes.byref(_geom(g)), f, vrc.shape[0], vrc, out)
+    return out
+
+
+def backproject_eq3(g, proj):
+    """The closed-form backprojection of Eq. (3) (section 2.2.2): per voxel
+    and view, dx dy dz / (du dv) L^3 / (L0 l^2) times g bilinearly
+    interpolated where the ray through the voxel centre meets the detector."""
+    proj = _f64(proj, _sino_shape(g))
+    out = np.empty(_vol_shape(g), np.float64)
+    _load().orc_backproject_eq3(ctypes.byref(_geom(g)), proj, out)
+    return out
+
+
+def backproject_eq3_voxels(g, proj, kji):
+    """``backproject_eq3`` at the listed voxels only; kji is (n, 3) int (k, j, i)."""
+    proj = _f64(proj, _sino_shape(g))
+    kji = np.ascontiguousarray(kji, dtype=np.int32).reshape(-1, 3)
+    out = np.empty(kji.shape[0], np.float64)
+    _load().orc_backproject_eq3_voxels(ctypes.byref(_geom(g)), proj, kji.shape[0], kji, out)
+    return out
+
+
 def framelet_analysis(f, dil=1):
     """W f: 27 bands (index 9n+3m+l) of the piecewise-linear tight frame (section 2.1)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
@@ -224,16 +268,17 @@ def framelet_shrink_voxels(f, lam, kji, levels=1, positivity=True):
     return out
 
 
-def cgls(g, x0, proj, n, history=False):
-    """n CGLS steps warm-started from x0 (Appendix 1).  Returns
+def cgls(g, x0, proj, n, history=False, op_pair=0):
+    """n CGLS steps warm-started from x0 (Appendix 1), with the Joseph pair
+    (op_pair 0) or the paper's Siddon / Eq. (3) pair (op_pair 1).  Returns
     (x, broke, resid2[, resid_hist])."""
     x = np.array(x0, dtype=np.float64, order="C", copy=True)
     assert x.shape == _vol_shape(g)
     proj = _f64(proj, _sino_shape(g))
     r2 = ctypes.c_double(0.0)
     hist = np.zeros(n + 1, np.float64) if history else None
-    broke = _load().orc_cgls(ctypes.byref(_geom(g)), x, proj, int(n), ctypes.byref(r2),
-                             hist.ctypes.data if history else None)
+    broke = _load().orc_cgls_pair(ctypes.byref(_geom(g)), int(op_pair), x, proj, int(n),
+                                  ctypes.byref(r2), hist.ctypes.data if history else None)
     if history:
         return x, bool(broke), r2.value, hist
     return x, bool(broke), r2.value
@@ -272,21 +317,23 @@ def prolong_vol(g_coarse, g_fine, vol):
     return out
 
 
-def _opts(lam, n_grids, iters, cgls_steps, framelet_levels, momentum, positivity, bin_detector):
+def _opts(lam, n_grids, iters, cgls_steps, framelet_levels, momentum, positivity, bin_detector,
+          op_pair=0):
     it = list(iters) + [0] * (4 - len(iters))
     return OrcOpts(float(lam), int(n_grids), (ctypes.c_int32 * 4)(*it), int(cgls_steps),
                    int(framelet_levels), int(bool(momentum)), int(bool(positivity)),
-                   int(bool(bin_detector)))
+                   int(bool(bin_detector)), int(op_pair))
 
 
 def reconstruct(g, proj, lam, iters, cgls_steps=3, framelet_levels=1, momentum=True,
-                positivity=True, bin_detector=True):
+                positivity=True, bin_detector=True, op_pair=0):
     """Algorithm A2 (A1 if momentum is False) in the multigrid schedule of
-    section 2.2.3; iters lists the outer iterations per grid, coarsest first.
+    section 2.2.3; iters lists the outer iterations per grid, coarsest first;
+    op_pair 1 takes the paper's Siddon / Eq. (3) operators.
     Returns (volume, report dict)."""
     proj = _f64(proj, _sino_shape(g))
     o = _opts(lam, len(iters), iters, cgls_steps, framelet_levels, momentum, positivity,
-              bin_detector)
+              bin_detector, op_pair)
     vol = np.empty(_vol_shape(g), np.float64)
     rep = OrcReport()
     rc = _load().orc_reconstruct(ctypes.byref(_geom(g)), ctypes.byref(o), proj, vol,
@@ -298,11 +345,12 @@ def reconstruct(g, proj, lam, iters, cgls_steps=3, framelet_levels=1, momentum=T
 
 
 def tf_iterations(g, proj, f0, n_iters, lam, cgls_steps=3, framelet_levels=1, momentum=True,
-                  positivity=True):
+                  positivity=True, op_pair=0):
     """n_iters outer iterations of Algorithm A2 on one grid from f_cur = f_prev = f0."""
     proj = _f64(proj, _sino_shape(g))
     vol = np.array(f0, dtype=np.float64, order="C", copy=True)
-    o = _opts(lam, 1, [n_iters], cgls_steps, framelet_levels, momentum, positivity, True)
+    o = _opts(lam, 1, [n_iters], cgls_steps, framelet_levels, momentum, positivity, True,
+              op_pair)
     rep = OrcReport()
     _load().orc_tf_iterations(ctypes.byref(_geom(g)), ctypes.byref(o), proj, int(n_iters), vol,
                               ctypes.byref(rep))

@@ -15,6 +15,8 @@
  *   Appendix 1                CGLS warm-started from v
  *   section 2.1, Alg. A1/A2   the outer iteration, A2 with the t-momentum
  *   section 2.2.3             the coarse-to-fine multigrid schedule
+ *   section 2.2.1, Eq. (3)    optionally, the paper's own operator pair:
+ *                             Siddon's P with the closed-form backprojection
  *
  * Readings where the paper is silent (each one is listed with its reason in
  * the design notes of the repository):
@@ -246,6 +248,203 @@ void orc_backproject_voxels(const orc_geom* g, const double* proj, int64_t n,
 }
 
 /* ------------------------------------------------------------------------- */
+/* The paper's own operator pair (section 2.2.1 and Eq. (3))                  */
+/* ------------------------------------------------------------------------- */
+/* Ray (c, r) of view v: source s and a = pixel - source (section 2.1 geometry
+ * reading above). */
+static void ray_vectors(const orc_geom* g, const view_t* v, int c, int r, double s[3],
+                        double a[3]) {
+  double uc = ((double)c - 0.5 * (g->nu - 1)) * g->du;
+  double vr = ((double)r - 0.5 * (g->nv - 1)) * g->dv;
+  s[0] = v->sx;
+  s[1] = v->sy;
+  s[2] = 0.0;
+  a[0] = -g->sdd * v->cs - uc * v->sn;
+  a[1] = -g->sdd * v->sn + uc * v->cs;
+  a[2] = vr;
+}
+
+static int cmp_double(const void* x, const void* y) {
+  double a = *(const double*)x, b = *(const double*)y;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Siddon's method (section 2.2.1): the voxels are boxes of size dx dy dz
+ * centred on the voxel centres; the line integral of Eq. (1) over the
+ * piecewise-constant volume is the sum over voxels of the value times the
+ * length of the source-to-pixel segment inside the box.  The segment
+ * s + alpha a, alpha in [0, 1], is cut at every box face it crosses (the
+ * parameters alpha of its crossings with the x, y and z face planes,
+ * sorted); each piece lies in one voxel.  Along an axis the piece's voxel
+ * index follows from how many of that axis's face crossings lie before the
+ * piece (the same alpha values that cut it, so a ray almost parallel to a
+ * face is never put on the wrong side by rounding).  Boxes are half-open,
+ * so a ray lying on a face plane between two voxels is counted once, in the
+ * upper one.  `work` holds 2 (nx + ny + nz) + 8 doubles. */
+static double siddon_ray(const orc_geom* g, const view_t* v, int c, int r, const double* f,
+                         double* work) {
+  double s[3], a[3];
+  ray_vectors(g, v, c, r, s, a);
+  const int n[3] = {g->nx, g->ny, g->nz};
+  const double d[3] = {g->dx, g->dy, g->dz};
+  double lo[3];
+  for (int ax = 0; ax < 3; ++ax) lo[ax] = -0.5 * n[ax] * d[ax];
+  /* face crossings per axis, in increasing alpha */
+  double* face[3];
+  face[0] = work;
+  face[1] = face[0] + n[0] + 1;
+  face[2] = face[1] + n[1] + 1;
+  double* cuts = face[2] + n[2] + 1;
+  int fixed[3]; /* voxel index along an axis the ray does not move along */
+  for (int ax = 0; ax < 3; ++ax) {
+    fixed[ax] = -1;
+    if (a[ax] == 0.0) {
+      int cnt = 0;
+      for (int b = 0; b <= n[ax]; ++b)
+        if (lo[ax] + b * d[ax] <= s[ax]) ++cnt;
+      if (cnt == 0 || cnt == n[ax] + 1) return 0.0; /* outside [lower, upper) */
+      fixed[ax] = cnt - 1;
+      continue;
+    }
+    for (int b = 0; b <= n[ax]; ++b) {
+      int bb = a[ax] > 0.0 ? b : n[ax] - b;
+      face[ax][b] = (lo[ax] + bb * d[ax] - s[ax]) / a[ax];
+    }
+  }
+  /* the part of [0, 1] inside the box: between the last entry and the first
+   * exit over the moving axes */
+  double amin = 0.0, amax = 1.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (fixed[ax] >= 0) continue;
+    if (face[ax][0] > amin) amin = face[ax][0];
+    if (face[ax][n[ax]] < amax) amax = face[ax][n[ax]];
+  }
+  if (!(amax > amin)) return 0.0;
+  int m = 0;
+  cuts[m++] = amin;
+  cuts[m++] = amax;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (fixed[ax] >= 0) continue;
+    for (int b = 0; b <= n[ax]; ++b)
+      if (face[ax][b] > amin && face[ax][b] < amax) cuts[m++] = face[ax][b];
+  }
+  qsort(cuts, (size_t)m, sizeof(double), cmp_double);
+  double alen = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  int cnt[3] = {0, 0, 0};
+  double sum = 0.0;
+  for (int q = 0; q + 1 < m; ++q) {
+    double w = cuts[q + 1] - cuts[q];
+    if (!(w > 0.0)) continue;
+    double mid = 0.5 * (cuts[q] + cuts[q + 1]);
+    int idx[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      if (fixed[ax] >= 0) {
+        idx[ax] = fixed[ax];
+        continue;
+      }
+      while (cnt[ax] <= n[ax] && face[ax][cnt[ax]] < mid) ++cnt[ax];
+      int t = a[ax] > 0.0 ? cnt[ax] - 1 : n[ax] - cnt[ax];
+      idx[ax] = t < 0 ? 0 : (t >= n[ax] ? n[ax] - 1 : t);
+    }
+    sum += f[((int64_t)idx[2] * g->ny + idx[1]) * g->nx + idx[0]] * w * alen;
+  }
+  return sum;
+}
+
+static int siddon_work(const orc_geom* g) { return 2 * (g->nx + g->ny + g->nz) + 8; }
+
+void orc_project_siddon(const orc_geom* g, const double* f, double* proj) {
+  int nu = g->nu, nv = g->nv;
+  for (int k = 0; k < g->n_views; ++k) {
+    view_t v = make_view(g, k);
+    double* out = proj + (int64_t)k * nu * nv;
+#pragma omp parallel
+    {
+      double* al = (double*)malloc(sizeof(double) * (size_t)siddon_work(g));
+#pragma omp for schedule(dynamic, 4)
+      for (int r = 0; r < nv; ++r)
+        for (int c = 0; c < nu; ++c) out[(int64_t)r * nu + c] = siddon_ray(g, &v, c, r, f, al);
+      free(al);
+    }
+  }
+}
+
+void orc_project_siddon_rays(const orc_geom* g, const double* f, int64_t n,
+                             const int32_t* vrc, double* out) {
+#pragma omp parallel
+  {
+    double* al = (double*)malloc(sizeof(double) * (size_t)siddon_work(g));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n; ++q) {
+      view_t v = make_view(g, vrc[3 * q]);
+      out[q] = siddon_ray(g, &v, vrc[3 * q + 2], vrc[3 * q + 1], f, al);
+    }
+    free(al);
+  }
+}
+
+/* Eq. (3): [P^T g](x) = dx dy dz / (du dv) sum_theta L^3(u*) / (L0 l^2(x))
+ * g(u*), with u* where the line from the source through x meets the
+ * detector, L(u*) = |u* - source|, l(x) = |x - source|, L0 = SDD; g(u*) by
+ * bilinear interpolation of the pixel-centre samples (section 2.2.2); taps
+ * that fall off the detector read zero. */
+static double eq3_voxel(const orc_geom* g, const double* proj, int i, int j, int k) {
+  double x = ((double)i - 0.5 * (g->nx - 1)) * g->dx;
+  double y = ((double)j - 0.5 * (g->ny - 1)) * g->dy;
+  double z = ((double)k - 0.5 * (g->nz - 1)) * g->dz;
+  int nu = g->nu, nv = g->nv;
+  double sum = 0.0;
+  for (int vw = 0; vw < g->n_views; ++vw) {
+    view_t v = make_view(g, vw);
+    /* distance from the source to x along the central ray, magnification */
+    double w = g->sad - (x * v.cs + y * v.sn);
+    if (!(w > 0.0)) continue;
+    double mag = g->sdd / w;
+    double us = mag * (-x * v.sn + y * v.cs), vs = mag * z;
+    double L = sqrt(g->sdd * g->sdd + us * us + vs * vs);
+    double l2 = (x - v.sx) * (x - v.sx) + (y - v.sy) * (y - v.sy) + z * z;
+    double fc = us / g->du + 0.5 * (nu - 1), fr = vs / g->dv + 0.5 * (nv - 1);
+    int c0 = (int)floor(fc), r0 = (int)floor(fr);
+    double wc = fc - c0, wr = fr - r0;
+    const double* in = proj + (int64_t)vw * nu * nv;
+    double gv = 0.0;
+    for (int rr = 0; rr <= 1; ++rr)
+      for (int cc = 0; cc <= 1; ++cc) {
+        int c = c0 + cc, r = r0 + rr;
+        if (c < 0 || c >= nu || r < 0 || r >= nv) continue;
+        gv += (cc ? wc : 1.0 - wc) * (rr ? wr : 1.0 - wr) * in[(int64_t)r * nu + c];
+      }
+    sum += L * L * L / (g->sdd * l2) * gv;
+  }
+  return g->dx * g->dy * g->dz / (g->du * g->dv) * sum;
+}
+
+void orc_backproject_eq3(const orc_geom* g, const double* proj, double* f) {
+  int nx = g->nx, ny = g->ny, nz = g->nz;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) f[((int64_t)k * ny + j) * nx + i] = eq3_voxel(g, proj, i, j, k);
+}
+
+void orc_backproject_eq3_voxels(const orc_geom* g, const double* proj, int64_t n,
+                                const int32_t* kji, double* out) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n; ++q) out[q] = eq3_voxel(g, proj, kji[3 * q + 2], kji[3 * q + 1], kji[3 * q]);
+}
+
+/* Operator pair selection: 0 = Joseph P with its exact transpose, 1 = the
+ * paper's Siddon P with the Eq. (3) backprojection. */
+static void pair_project(int pair, const orc_geom* g, const double* f, double* proj) {
+  if (pair == 1) orc_project_siddon(g, f, proj);
+  else orc_project(g, f, proj);
+}
+static void pair_backproject(int pair, const orc_geom* g, const double* proj, double* f) {
+  if (pair == 1) orc_backproject_eq3(g, proj, f);
+  else orc_backproject(g, proj, f);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Tight frame (section 2.1): h0 = [1,2,1]/4, h1 = sqrt(2)/4 [1,0,-1],        */
 /* h2 = [-1,2,-1]/4; band i = 9n + 3m + l is h_l(x) h_m(y) h_n(z).            */
 /* ------------------------------------------------------------------------- */
@@ -434,6 +633,11 @@ void orc_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t levels,
 /* ------------------------------------------------------------------------- */
 int orc_cgls(const orc_geom* g, double* x, const double* proj, int32_t n,
              double* resid2, double* resid_hist) {
+  return orc_cgls_pair(g, 0, x, proj, n, resid2, resid_hist);
+}
+
+int orc_cgls_pair(const orc_geom* g, int32_t pair, double* x, const double* proj, int32_t n,
+                  double* resid2, double* resid_hist) {
   int64_t V = (int64_t)g->nx * g->ny * g->nz;
   int64_t S = (int64_t)g->n_views * g->nu * g->nv;
   double* r = (double*)malloc(sizeof(double) * (size_t)S);
@@ -443,18 +647,18 @@ int orc_cgls(const orc_geom* g, double* x, const double* proj, int32_t n,
   const double tiny = 1e-300;
   int broke = 0;
 
-  orc_project(g, x, r);
+  pair_project(pair, g, x, r);
   for (int64_t i = 0; i < S; ++i) r[i] = proj[i] - r[i];
   if (resid_hist) {
     for (int l = 0; l <= n; ++l) resid_hist[l] = NAN;
     resid_hist[0] = dot(r, r, S);
   }
-  orc_backproject(g, r, s);
+  pair_backproject(pair, g, r, s);
   memcpy(p, s, sizeof(double) * (size_t)V);
   double gamma = dot(s, s, V);
 
   for (int l = 0; l < n; ++l) {
-    orc_project(g, p, q);
+    pair_project(pair, g, p, q);
     double delta = dot(q, q, S);
     if (gamma <= tiny || delta <= tiny) {
       broke = 1;
@@ -465,7 +669,7 @@ int orc_cgls(const orc_geom* g, double* x, const double* proj, int32_t n,
     for (int64_t i = 0; i < S; ++i) r[i] -= alpha * q[i];
     if (resid_hist) resid_hist[l + 1] = dot(r, r, S);
     if (l < n - 1) {
-      orc_backproject(g, r, s);
+      pair_backproject(pair, g, r, s);
       double gnew = dot(s, s, V);
       double beta = gnew / gamma;
       for (int64_t i = 0; i < V; ++i) p[i] = s[i] + beta * p[i];
@@ -577,7 +781,7 @@ int orc_tf_iterations(const orc_geom* g, const orc_opts* o, const double* proj,
     double c = o->momentum ? (t_prev - 1.0) / t_cur : 0.0;
     for (int64_t i = 0; i < V; ++i) x[i] = f_cur[i] + c * (f_cur[i] - f_prev[i]);
     double r2 = 0.0;
-    int broke = orc_cgls(g, x, proj, o->cgls_steps, &r2, NULL);
+    int broke = orc_cgls_pair(g, o->op_pair, x, proj, o->cgls_steps, &r2, NULL);
     if (rep) {
       rep->cgls_breakdowns += broke;
       rep->resid2_last = r2;

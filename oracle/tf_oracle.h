@@ -40,6 +40,7 @@ typedef struct {
   int32_t momentum;     /* 1 = Algorithm A2, 0 = Algorithm A1 */
   int32_t positivity;   /* 1 = apply H */
   int32_t bin_coarse_detector; /* 1 = 2x2 detector binning on coarser grids */
+  int32_t op_pair;      /* 0 = Joseph P + exact transpose, 1 = Siddon P + Eq. (3) */
 } orc_opts;
 
 typedef struct {
@@ -61,6 +62,17 @@ void orc_backproject(const orc_geom* g, const double* proj, double* f);
 void orc_backproject_voxels(const orc_geom* g, const double* proj, int64_t n,
                             const int32_t* kji, double* out);
 
+/* The paper's operator pair (section 2.2.1, Eq. (3)): Siddon's exact
+ * radiological path through voxel boxes, and the closed-form voxel-driven
+ * backprojection with bilinear detector interpolation (not the transpose of
+ * either projector). */
+void orc_project_siddon(const orc_geom* g, const double* f, double* proj);
+void orc_project_siddon_rays(const orc_geom* g, const double* f, int64_t n,
+                             const int32_t* vrc, double* out);
+void orc_backproject_eq3(const orc_geom* g, const double* proj, double* f);
+void orc_backproject_eq3_voxels(const orc_geom* g, const double* proj, int64_t n,
+                                const int32_t* kji, double* out);
+
 /* Framelet analysis W of one level: coeff[27][nz][ny][nx], band 9n+3m+l. */
 void orc_framelet_analysis(int32_t nx, int32_t ny, int32_t nz, int32_t dil,
                            const double* f, double* coeff);
@@ -80,6 +92,9 @@ void orc_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t levels,
  * residual norm^2 after init and after each step. */
 int orc_cgls(const orc_geom* g, double* x, const double* proj, int32_t n,
              double* resid2, double* resid_hist);
+/* The same with the operator pair chosen (0 Joseph/transpose, 1 Siddon/Eq. (3)). */
+int orc_cgls_pair(const orc_geom* g, int32_t pair, double* x, const double* proj, int32_t n,
+                  double* resid2, double* resid_hist);
 
 /* Multigrid transfer operators (section 2.2.3). */
 void orc_coarse_geom(const orc_geom* fine, int32_t bin_detector, orc_geom* coarse);

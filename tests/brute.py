@@ -111,3 +111,87 @@ def shrink_dense(coeff, lam):
     s = np.where(nrm <= lam, 0.0, 1.0 - lam / np.where(nrm > 0, nrm, 1.0))
     c[1:] *= s
     return c
+
+
+def _view_frame(g, th):
+    ct, st = math.cos(th), math.sin(th)
+    src = np.array([g.sad * ct, g.sad * st, 0.0])
+    det_c = -(g.sdd - g.sad) * np.array([ct, st, 0.0])
+    e_u = np.array([-st, ct, 0.0])
+    e_v = np.array([0.0, 0.0, 1.0])
+    return src, det_c, e_u, e_v
+
+
+def _voxel_boxes(g):
+    """Lower and upper corners of every voxel box, each (nz, ny, nx, 3)."""
+    ii = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.dx
+    jj = (np.arange(g.ny) - (g.ny - 1) / 2.0) * g.dy
+    kk = (np.arange(g.nz) - (g.nz - 1) / 2.0) * g.dz
+    K, J, I = np.meshgrid(kk, jj, ii, indexing="ij")
+    ctr = np.stack([I, J, K], axis=-1)
+    half = 0.5 * np.array([g.dx, g.dy, g.dz])
+    return ctr - half, ctr + half
+
+
+def siddon_matrix(g) -> np.ndarray:
+    """The radiological-path projector: entry (ray, voxel) is the length of
+    the source-to-pixel segment inside the voxel's box, from the slab
+    intersection of the segment with each box separately (no traversal).
+    Boxes are half-open: a ray lying on a face plane counts in the box above."""
+    lo, hi = _voxel_boxes(g)
+    rows = []
+    for th in view_angles(g):
+        src, det_c, e_u, e_v = _view_frame(g, th)
+        for r in range(g.nv):
+            for c in range(g.nu):
+                pix = det_c + (c - (g.nu - 1) / 2.0) * g.du * e_u + (r - (g.nv - 1) / 2.0) * g.dv * e_v
+                a = pix - src
+                t_in = np.zeros(lo.shape[:3])
+                t_out = np.ones(lo.shape[:3])
+                for ax in range(3):
+                    if a[ax] == 0.0:
+                        # half-open boxes: a ray on a face belongs to the box above it
+                        inside = (src[ax] >= lo[..., ax]) & (src[ax] < hi[..., ax])
+                        t_out = np.where(inside, t_out, -1.0)
+                        continue
+                    t0 = (lo[..., ax] - src[ax]) / a[ax]
+                    t1 = (hi[..., ax] - src[ax]) / a[ax]
+                    t_in = np.maximum(t_in, np.minimum(t0, t1))
+                    t_out = np.minimum(t_out, np.maximum(t0, t1))
+                rows.append((np.maximum(t_out - t_in, 0.0) * np.linalg.norm(a)).reshape(-1))
+    return np.array(rows)
+
+
+def detector_hit(g, th, pts):
+    """Where the lines from the source through points pts (n, 3) meet the
+    detector plane: (u*, v*, L, l) from the 3D line-plane intersection."""
+    src, det_c, e_u, e_v = _view_frame(g, th)
+    nrm = np.cross(e_u, e_v)  # detector normal
+    d = pts - src
+    t = ((det_c - src) @ nrm) / (d @ nrm)
+    hit = src + t[:, None] * d
+    rel = hit - det_c
+    return rel @ e_u, rel @ e_v, np.linalg.norm(hit - src, axis=1), np.linalg.norm(d, axis=1)
+
+
+def eq3_matrix(g) -> np.ndarray:
+    """The Eq. (3) backprojection as a dense (voxel, ray) matrix: for every
+    voxel centre and view, dx dy dz / (du dv) L^3 / (SDD l^2) times the
+    bilinear weights (products of hats in pixel units) of the detector
+    pixels around the hit point."""
+    ii = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.dx
+    jj = (np.arange(g.ny) - (g.ny - 1) / 2.0) * g.dy
+    kk = (np.arange(g.nz) - (g.nz - 1) / 2.0) * g.dz
+    K, J, I = np.meshgrid(kk, jj, ii, indexing="ij")
+    pts = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+    uc = (np.arange(g.nu) - (g.nu - 1) / 2.0) * g.du
+    vr = (np.arange(g.nv) - (g.nv - 1) / 2.0) * g.dv
+    pref = g.dx * g.dy * g.dz / (g.du * g.dv)
+    blocks = []
+    for th in view_angles(g):
+        us, vs, L, l = detector_hit(g, th, pts)
+        wu = hat((us[:, None] - uc[None, :]) / g.du)  # (voxels, nu)
+        wv = hat((vs[:, None] - vr[None, :]) / g.dv)  # (voxels, nv)
+        scale = pref * L ** 3 / (g.sdd * l ** 2)
+        blocks.append((scale[:, None, None] * wv[:, :, None] * wu[:, None, :]).reshape(len(pts), -1))
+    return np.concatenate(blocks, axis=1)
