@@ -84,6 +84,11 @@ typedef struct {
                                arithmetic is FP32, reductions FP64 */
   int32_t profile;          /* 1 = time every P, P^T and framelet launch with
                                HIP events on `stream` (fills kernel_ms) */
+  int32_t op_pair;          /* operators of the CGLS step: 0 = Joseph P with its
+                               exact transpose (tfcb_project / tfcb_backproject);
+                               1 = the paper's pair, Siddon P with the Eq. (3)
+                               backprojection in place of P^T
+                               (tfcb_project_siddon / tfcb_backproject_eq3) */
 } tfcb_options;
 
 typedef struct {
@@ -130,6 +135,26 @@ tfcb_status tfcb_project(const tfcb_geometry* g, tfcb_dtype dt, const void* vol,
 tfcb_status tfcb_backproject(const tfcb_geometry* g, tfcb_dtype dt, const void* proj, void* vol,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* proj = P vol by Siddon's ray tracing (section 2.2.1), the paper's
+ * projector: voxels are boxes of size dx dy dz around the voxel centres
+ * (half-open along each axis, so a ray lying on a face between two voxels
+ * counts in the upper one); each ray sums the voxel values times the length
+ * of its source-to-pixel segment inside each box.  vol, proj: device,
+ * storage dt.  ws: as for tfcb_project. */
+tfcb_status tfcb_project_siddon(const tfcb_geometry* g, tfcb_dtype dt, const void* vol,
+                                void* proj, void* ws, size_t ws_bytes, void* stream);
+
+/* vol = the closed-form backprojection of Eq. (3) (section 2.2.2, Appendix
+ * 2): per voxel centre x and view, dx dy dz / (du dv) L^3 / (SDD l^2) times
+ * proj bilinearly interpolated where the ray from the source through x meets
+ * the detector (pixel-centre samples; taps off the detector read zero);
+ * L = source-to-hit distance, l = source-to-voxel distance.  Not the
+ * transpose of either projector (the paper reports under 1 % adjoint
+ * mismatch against ray tracing).  proj, vol: device, storage dt.  ws: as for
+ * tfcb_backproject. */
+tfcb_status tfcb_backproject_eq3(const tfcb_geometry* g, tfcb_dtype dt, const void* proj,
+                                 void* vol, void* ws, size_t ws_bytes, void* stream);
+
 /* out = H(W^T T_lambda W in) (section 2.1: the 27-band piecewise-linear
  * tight frame, the vector shrinkage of Eq. (2), positivity H when
  * positivity = 1).  W is convolution with half-sample symmetric extension and
@@ -148,7 +173,8 @@ tfcb_status tfcb_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t lev
  * last step) s = P^T r, beta = ||s||^2 / gamma, p = s + beta p.  The call
  * stops early (x left as is) when gamma or ||q||^2 <= 1e-300.  Reductions in
  * FP64.  x: device volume, proj: device projections, storage o->storage;
- * only o->storage and o->cgls_steps of `o` are used.  stats (nullable,
+ * only o->storage, o->cgls_steps and o->op_pair of `o` are used (op_pair 1
+ * takes the Eq. (3) backprojection in place of P^T).  stats (nullable,
  * HOST, written after a stream synchronisation): [0] = ||r||^2 at exit,
  * [1] = 1 if the guard stopped the call. */
 tfcb_status tfcb_cgls(const tfcb_geometry* g, const tfcb_options* o, void* x, const void* proj,

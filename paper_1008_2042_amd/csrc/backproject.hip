@@ -29,6 +29,58 @@ namespace tfcb {
 constexpr int kZRun = 8;     // voxels per thread along z
 constexpr int kTile = 6144;  // LDS floats for one view's staged footprint (24 KB)
 
+// One detector column's contribution to the K voxels of a z-run, with trans
+// weight wt.  Segment m = 0..K holds the rows whose z index
+// zh_r = tau vz_r + zc has floor k0 - 1 + m; they give (1 - fr) of their
+// value to voxel k0 - 1 + m and fr to voxel k0 + m, fr = zh_r - (k0 - 1 + m).
+// Rows are read from `col` (row r at col[(r - row0) * stride]) over
+// [rb, r1].  Segment bounds come from the inverse of the row map; a row
+// misplaced by rounding at a bound has fr within an ulp of 0 or 1, so its
+// weights are still right.  Within a segment fr grows by zstep = tau dv/dz
+// per row, so with the first row's fraction f_b (the projector's
+// expression) only sum g and sum (r - r_b) g are accumulated:
+// sum fr g = f_b sum g + zstep sum (r - r_b) g.  Each segment is added to
+// its two voxels as soon as it is complete.
+template <int K, typename P>
+__device__ __forceinline__ void column_to_run(const P* __restrict__ col, int stride, int row0,
+                                              int r1, int rb, int k0, float tau, float zstep,
+                                              float inv_s, float zc, float rc, float wt,
+                                              const float* __restrict__ vz_tab, int nv,
+                                              float (&acc)[K]) {
+  float base = (float)(k0 - 1);  // z index of segment m's lower voxel
+#pragma unroll
+  for (int m = 0; m <= K; ++m) {
+    // opaque to the optimiser, so each segment's bound and fraction are
+    // computed where they are used instead of all K + 1 being hoisted ahead
+    // of the row loops (which would hold them in registers)
+    asm volatile("" : "+v"(base));
+    const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
+    float a0 = 0.f, a1 = 0.f, fo = 0.f;
+    const P* __restrict__ gp = col + (size_t)(rb - row0) * stride;
+    int r = rb;
+    for (; r + 1 < re; r += 2) {
+      const float g0 = ld(gp), g1 = ld(gp + stride);
+      gp += 2 * stride;
+      a0 += g0;
+      a1 = fmaf(fo, g0, a1);
+      a0 += g1;
+      a1 = fmaf(fo + 1.f, g1, a1);
+      fo += 2.f;
+    }
+    if (r < re) {
+      const float g0 = ld(gp);
+      a0 += g0;
+      a1 = fmaf(fo, g0, a1);
+    }
+    const float fb = fmaf(tau, vz_tab[min(rb, nv - 1)], zc) - base;
+    const float s1 = fmaf(fb, a0, zstep * a1);  // sum fr g
+    if (m > 0) acc[m - 1] = fmaf(wt, a0 - s1, acc[m - 1]);
+    if (m < K) acc[m] = fmaf(wt, s1, acc[m]);
+    rb = re;
+    base += 1.f;
+  }
+}
+
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
                                                      const ColInfo* __restrict__ cols,
@@ -93,9 +145,27 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
     const int W = c1 - c0 + 1, H = r1 - r0 + 1;
     const bool staged = W > 0 && H > 0 && W * H <= kTile;
     if (staged) {
-      for (int rr = wave; rr < H; rr += 4) {
-        const T* src = rview + (size_t)(r0 + rr) * g.nu + c0;
-        for (int cc = lane; cc < W; cc += 64) tile[rr * W + cc] = ld(src + cc);
+      // each wave takes rows wave, wave + 4, ...; a lane loads 4 rows x 2
+      // columns before it writes any, so 8 loads per lane are in flight
+      for (int cb = 0; cb < W; cb += 128) {
+        for (int rr = wave; rr < H; rr += 16) {
+          float v[4][2];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int row = rr + 4 * u, cc = cb + lane + 64 * h;
+              v[u][h] = (row < H && cc < W) ? ld(rview + (size_t)(r0 + row) * g.nu + (c0 + cc))
+                                            : 0.f;
+            }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int row = rr + 4 * u, cc = cb + lane + 64 * h;
+              if (row < H && cc < W) tile[row * W + cc] = v[u][h];
+            }
+        }
       }
     }
     __syncthreads();
@@ -140,52 +210,17 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
       const float wt = 1.f - fabsf(th - (float)t);
       if (wt <= 0.f) continue;
       const float tau = fmaf(fp, h0.w, h0.z);
-      // The z index of row r is zh_r = tau vz_r + zc (increasing in r).
-      // Segment m = the rows with floor(zh_r) = k0 - 1 + m, m = 0..K: its
-      // rows give (1 - fr) of their value to voxel k0 - 1 + m and fr to
-      // voxel k0 + m, fr = zh_r - (k0 - 1 + m).  Segment bounds come from
-      // the inverse of the row map; a row misplaced by rounding at a bound
-      // has fr within an ulp of 0 or 1, so its weights are still right.
-      const float inv_s = __builtin_amdgcn_rcpf(tau * g.dvdz);
-      float s0[K + 1], s1[K + 1];
-      int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
-      if (staged) {
-        const int tc = c - c0;  // tile column; tile row = r - r0
-#pragma unroll
-        for (int m = 0; m <= K; ++m) {
-          const float base = (float)(k0 - 1 + m);
-          const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
-          float a0 = 0.f, a1 = 0.f;
-          for (int r = rb; r < re; ++r) {
-            const float fr = fmaf(tau, vz_tab[r], zc) - base;
-            const float gv = tile[(r - r0) * W + tc];
-            a0 += gv;
-            a1 = fmaf(fr, gv, a1);
-          }
-          s0[m] = a0;
-          s1[m] = a1;
-          rb = re;
-        }
-      } else {
-        const T* __restrict__ colp = rview + c;
-#pragma unroll
-        for (int m = 0; m <= K; ++m) {
-          const float base = (float)(k0 - 1 + m);
-          const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
-          float a0 = 0.f, a1 = 0.f;
-          for (int r = rb; r < re; ++r) {
-            const float fr = fmaf(tau, vz_tab[r], zc) - base;
-            const float gv = ld(colp + (size_t)r * g.nu);
-            a0 += gv;
-            a1 = fmaf(fr, gv, a1);
-          }
-          s0[m] = a0;
-          s1[m] = a1;
-          rb = re;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fmaf(wt, s1[q] + (s0[q + 1] - s1[q + 1]), acc[q]);
+      // Segment m = the rows of z index in [k0 - 1 + m, k0 + m): they give
+      // (1 - fr) of their value to voxel k0 - 1 + m and fr to voxel k0 + m.
+      const float zstep = tau * g.dvdz;
+      const float inv_s = __builtin_amdgcn_rcpf(zstep);
+      const int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
+      if (staged)
+        column_to_run<K>(tile + (c - c0), W, r0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
+                         g.nv, acc);
+      else
+        column_to_run<K>(rview + c, g.nu, 0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
+                         g.nv, acc);
     }
   }
 

@@ -75,7 +75,7 @@ tfcb_status validate_geometry(const tfcb_geometry* g) {
     return fail(TFCB_EUNSUPPORTED, "an axis exceeds 65535");
   if (g->nv > 16384 || g->nu > 65535)
     return fail(TFCB_EUNSUPPORTED, "detector larger than 65535 x 16384 pixels");
-  const double pad = (double)(g->nz + 2) * std::max(g->nx, g->ny) * (std::max(g->nx, g->ny) + 1);
+  const double pad = (double)(g->nz + 2 * kZPad) * std::max(g->nx, g->ny) * (std::max(g->nx, g->ny) + 1);
   if (pad >= 2147483647.0)
     return fail(TFCB_EUNSUPPORTED, "padded volume copy exceeds 2^31 elements");
   if (g->angles)
@@ -102,6 +102,7 @@ tfcb_status validate_options(const tfcb_options* o) {
   if (o->framelet_levels != 1 && o->framelet_levels != 2)
     return fail(TFCB_EINVAL, "framelet_levels must be 1 or 2");
   TFCB_TRY(validate_dtype(o->storage));
+  if (o->op_pair != 0 && o->op_pair != 1) return fail(TFCB_EINVAL, "op_pair must be 0 or 1");
   return TFCB_OK;
 }
 
@@ -165,6 +166,7 @@ struct GridBufs {
   void *g, *r, *rl, *q;         // projections
   double* partials;
   int max_partials;
+  int op_pair;  // 0: Joseph P + exact transpose; 1: Siddon P + Eq. (3)
 };
 
 struct Plan {
@@ -191,6 +193,7 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
     GridBufs& b = P.grid[l];
     b.geom = cur;
     b.gd = make_geom_dev(cur);
+    b.op_pair = o.op_pair;
     b.views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * cur.n_views));
     b.cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)cur.n_views * cur.nu));
     const size_t V = nvox(cur) * es, S = npix(cur) * es;
@@ -275,6 +278,24 @@ struct Profiler {
   } while (0)
 
 // --------------------------------------------------------------- CGLS
+// The grid's operator pair: P of a direction held as its padded copies
+// (mode 1: r = g - P x with rl = l r for the Joseph pair; mode 2: q = P p),
+// and the backprojection that stands for P^T (the exact transpose of the
+// length-prescaled rl, or Eq. (3) of plain r).
+template <typename T>
+hipError_t pair_project(const GridBufs& b, const T* pN, const T* pT, int mode, const T* gin,
+                        T* out, T* rl, int* np, hipStream_t s) {
+  if (b.op_pair == 1)
+    return launch_project_siddon(b.gd, b.views, pN, mode, gin, out, b.partials, np, s);
+  return launch_project(b.gd, b.views, b.cols, pN, pT, mode, gin, out, rl, b.partials, np, s);
+}
+template <typename T>
+hipError_t pair_backproject(const GridBufs& b, const T* r, const T* rl, T* out, int* np,
+                            hipStream_t s) {
+  if (b.op_pair == 1) return launch_backproject_eq3(b.gd, b.views, r, out, b.partials, np, s);
+  return launch_backproject(b.gd, b.views, b.cols, rl, out, b.partials, np, s);
+}
+
 template <typename T>
 tfcb_status run_cgls(const GridBufs& b, CglsScalars* sc, T* x, const T* gin, int n,
                      hipStream_t s, Profiler* prof = nullptr) {
@@ -287,28 +308,27 @@ tfcb_status run_cgls(const GridBufs& b, CglsScalars* sc, T* x, const T* gin, int
   T* q = static_cast<T*>(b.q);
   int np = 0;
   const double nv = (double)g.nx * g.ny * g.nz;
-  // r = g - P x; rl = l r   (x reaches P through the padded copies)
+  // r = g - P x (rl = l r)   (x reaches P through the padded copies)
   TFCB_HIP(launch_pad_copies(g.nx, g.ny, g.nz, (const T*)x, pN, pT, s));
-  TFCB_TIMED(prof, 0, launch_project(g, b.views, b.cols, (const T*)pN, (const T*)pT, 1, gin, r,
-                                     rl, b.partials, &np, s));
+  TFCB_TIMED(prof, 0, pair_project(b, (const T*)pN, (const T*)pT, 1, gin, r, rl, &np, s));
   TFCB_HIP(launch_finalize(b.partials, np, FIN_RESID, sc, nv, s));
   // s = P^T r; gamma = ||s||^2
-  TFCB_TIMED(prof, 1, launch_backproject(g, b.views, b.cols, rl, sv, b.partials, &np, s));
+  TFCB_TIMED(prof, 1, pair_backproject(b, (const T*)r, (const T*)rl, sv, &np, s));
   TFCB_HIP(launch_finalize(b.partials, np, FIN_GAMMA_INIT, sc, nv, s));
   // pn = s / sigma, as its two padded copies
   TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 0, x, pN, pT, (const T*)sv, sc, s));
   for (int l = 0; l < n; ++l) {
     // q = P p; alpha = gamma / ||q||^2 (or stop)
-    TFCB_TIMED(prof, 0, launch_project(g, b.views, b.cols, (const T*)pN, (const T*)pT, 2,
-                                       static_cast<const T*>(nullptr), q,
-                                       static_cast<T*>(nullptr), b.partials, &np, s));
+    TFCB_TIMED(prof, 0, pair_project(b, (const T*)pN, (const T*)pT, 2,
+                                     static_cast<const T*>(nullptr), q, static_cast<T*>(nullptr),
+                                     &np, s));
     TFCB_HIP(launch_finalize(b.partials, np, FIN_ALPHA, sc, nv, s));
     // r -= alpha q; rl = l r
     TFCB_HIP(launch_residual_update(g, b.views, b.cols, r, q, rl, sc, b.partials, &np, s));
     TFCB_HIP(launch_finalize(b.partials, np, FIN_RESID, sc, nv, s));
     if (l < n - 1) {
       // s = P^T r; beta = ||s||^2 / gamma; x += alpha p; p = s + beta p
-      TFCB_TIMED(prof, 1, launch_backproject(g, b.views, b.cols, rl, sv, b.partials, &np, s));
+      TFCB_TIMED(prof, 1, pair_backproject(b, (const T*)r, (const T*)rl, sv, &np, s));
       TFCB_HIP(launch_finalize(b.partials, np, FIN_BETA, sc, nv, s));
       TFCB_HIP(launch_xp_update(g.nx, g.ny, g.nz, 1, x, pN, pT, (const T*)sv, sc, s));
     } else {

@@ -112,6 +112,62 @@ tfcb_status tfcb_backproject(const tfcb_geometry* g, tfcb_dtype dt, const void* 
   });
 }
 
+// Siddon P (section 2.2.1) of a native volume: its native padded copy is
+// built in the operator workspace, where tfcb_project keeps it too.
+tfcb_status tfcb_project_siddon(const tfcb_geometry* g, tfcb_dtype dt, const void* vol,
+                                void* proj, void* ws, size_t ws_bytes, void* stream) {
+  TFCB_TRY(validate_geometry(g));
+  TFCB_TRY(validate_dtype(dt));
+  TFCB_TRY(check_ptr(vol, "vol"));
+  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ws(ws, ws_bytes, operator_ws_bytes(*g, dt)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(dt, [&](auto tag) -> tfcb_status {
+    using T = decltype(tag);
+    Carver cv(ws);
+    double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
+    ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
+    ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
+    const size_t nN = pad_elems(g->ny, g->nx, g->nz), nT = pad_elems(g->nx, g->ny, g->nz);
+    T* padN = static_cast<T*>(cv.take(nN * sizeof(T)));
+    T* padT = static_cast<T*>(cv.take(nT * sizeof(T)));
+    const double* angd = nullptr;
+    TFCB_TRY(upload_angles(*g, ang, s, &angd));
+    TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
+    const GeomDev gd = make_geom_dev(*g);
+    TFCB_HIP(launch_fill(nN, 0.f, padN, s));
+    TFCB_HIP(launch_pad_copies(g->nx, g->ny, g->nz, static_cast<const T*>(vol), padN, padT, s));
+    TFCB_HIP(launch_project_siddon(gd, views, (const T*)padN, 0, static_cast<const T*>(nullptr),
+                                   static_cast<T*>(proj), nullptr, nullptr, s));
+    return TFCB_OK;
+  });
+}
+
+// The Eq. (3) backprojection (section 2.2.2) of plain projections.
+tfcb_status tfcb_backproject_eq3(const tfcb_geometry* g, tfcb_dtype dt, const void* proj,
+                                 void* vol, void* ws, size_t ws_bytes, void* stream) {
+  TFCB_TRY(validate_geometry(g));
+  TFCB_TRY(validate_dtype(dt));
+  TFCB_TRY(check_ptr(vol, "vol"));
+  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ws(ws, ws_bytes, operator_ws_bytes(*g, dt)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(dt, [&](auto tag) -> tfcb_status {
+    using T = decltype(tag);
+    Carver cv(ws);
+    double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
+    ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
+    ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
+    const double* angd = nullptr;
+    TFCB_TRY(upload_angles(*g, ang, s, &angd));
+    TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
+    const GeomDev gd = make_geom_dev(*g);
+    TFCB_HIP(launch_backproject_eq3(gd, views, static_cast<const T*>(proj), static_cast<T*>(vol),
+                                    nullptr, nullptr, s));
+    return TFCB_OK;
+  });
+}
+
 tfcb_status tfcb_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t levels, double lambda,
                                  int32_t positivity, tfcb_dtype dt, const void* in, void* out,
                                  void* ws, size_t ws_bytes, void* stream) {
@@ -146,6 +202,7 @@ tfcb_status tfcb_cgls(const tfcb_geometry* g, const tfcb_options* o, void* x, co
   if (!o) return fail(TFCB_EINVAL, "options is NULL");
   TFCB_TRY(validate_dtype(o->storage));
   if (o->cgls_steps < 1 || o->cgls_steps > 64) return fail(TFCB_EINVAL, "cgls_steps must be 1..64");
+  if (o->op_pair != 0 && o->op_pair != 1) return fail(TFCB_EINVAL, "op_pair must be 0 or 1");
   TFCB_TRY(check_ptr(x, "x"));
   TFCB_TRY(check_ptr(proj, "proj"));
   tfcb_options one = *o;

@@ -1,13 +1,19 @@
 // Forward projector P: the line integral of Eq. (1) discretised by Joseph's
-// method, one thread per ray.
+// method.
 //
-// Mapping: a 256-thread block covers 64 detector columns x 4 rows of one
-// view.  Each wavefront is one detector row; its 64 lanes are adjacent
-// columns, whose crossings with a plane of the stepping axis are adjacent in
-// the trans axis, which is the fastest axis of the volume copy the view
+// Mapping: a 256-thread block covers 64 detector columns x 4 RPT rows of one
+// view.  Each wavefront takes RPT adjacent detector rows; its 64 lanes are
+// adjacent columns, whose crossings with a plane of the stepping axis are
+// adjacent in the trans axis, the fastest axis of the volume copy the view
 // reads (native [z][y][x] for y-stepping views, [z][x][y] for x-stepping
-// views).  So the four bilinear taps of a plane are two short contiguous
-// runs per wavefront, and the four rows of a block share their z taps in L1.
+// views).  The rows of one column cross a plane at the same trans position
+// (it depends on the column only) and at z positions less than NL - 2 slices
+// apart, so one thread loads a stack of NL consecutive z levels of the plane
+// (one 8-byte load of the two trans taps per level), interpolates each level
+// in trans once, and takes every row's bilinear sample from the two levels
+// around it.  RPT = 1 (NL = 2) is the one-ray-per-thread kernel.
+#include <cmath>
+
 #include "tfcb_internal.h"
 
 namespace tfcb {
@@ -56,42 +62,70 @@ __device__ __forceinline__ void plane_range(const ColInfo& ci, float vz, float z
   while (hi >= lo && !sample_inside(ci, hi, vz, zc, nt, nz)) --hi;
 }
 
-// One plane sample: bilinear interpolation of the padded copy `vb` (pointer
-// at element (0, 0, 0)), trans stride 1, plane stride ntp, z stride zs.
-template <typename T>
-__device__ __forceinline__ float sample(const T* __restrict__ vb, const ColInfo& ci, int p,
-                                        float vz, float zc, int nt, int nz, int ns, int ntp,
-                                        int zs) {
+// The samples of plane p for the RPT rows of one column (row j's z factor
+// vz[j], increasing in j).  The padded copy `vb` points at element
+// (0, 0, 0); trans stride 1, plane stride ntp, z stride zs.
+//
+// Within the union of the rows' plane windows the lowest row's z index is
+// above -(NL - 1) and below nz, so the NL levels from its floor lie in
+// [-kZPad, nz + kZPad) (the host picks RPT and NL so that the rows span fewer
+// than NL - 2 slices).  A row outside its own window there has both taps in
+// the zero pads, or one with weight exactly zero, and adds exactly 0; inside
+// its window its sample is the one-ray bilinear sample bit for bit.
+template <typename T, int RPT, int NL>
+__device__ __forceinline__ void sample_rows(const T* __restrict__ vb, const ColInfo& ci, int p,
+                                            const float (&vz)[RPT], float zc, int nt, int nz,
+                                            int ns, int ntp, int zs, float (&acc)[RPT]) {
   const float th = trans_index(ci, p);
-  const float zh = z_index(ci, p, vz, zc);
-  const float tf = floorf(th), zf = floorf(zh);
-  // inside the plane window these are already in [-1, nt-1] and [-1, nz-1];
-  // the clamps only guarantee in-buffer addresses
+  const float tf = floorf(th);
+  // inside the window it is already in [-1, nt-1]; the clamps only
+  // guarantee in-buffer addresses
   const int it = min(max((int)tf, -1), nt - 1);
-  const int iz = min(max((int)zf, -1), nz - 1);
-  const float wt = th - tf, wz = zh - zf;
-  const int o = (iz * ns + p) * ntp + it;
-  const float v00 = ld(vb + o), v01 = ld(vb + o + 1);
-  const float v10 = ld(vb + o + zs), v11 = ld(vb + o + zs + 1);
-  const float a = fmaf(wt, v01 - v00, v00);
-  const float b = fmaf(wt, v11 - v10, v10);
-  return fmaf(wz, b - a, a);
+  const float wt = th - tf;
+  float zh[RPT], zf[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    zh[j] = z_index(ci, p, vz[j], zc);
+    zf[j] = floorf(zh[j]);
+  }
+  const int iz0 = min(max((int)zf[0], -kZPad), nz - 1);
+  const T* __restrict__ q = vb + ((iz0 * ns + p) * ntp + it);
+  float lev[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const float v0 = ld(q + l * zs), v1 = ld(q + l * zs + 1);
+    lev[l] = fmaf(wt, v1 - v0, v0);
+  }
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    float lo = lev[0], up = lev[1];
+    if (j > 0) {
+      const int d = (int)zf[j] - iz0;
+#pragma unroll
+      for (int l = 1; l < NL - 1; ++l)
+        if (d >= l) {
+          lo = lev[l];
+          up = lev[l + 1];
+        }
+    }
+    acc[j] += fmaf(zh[j] - zf[j], up - lo, lo);
+  }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int RPT, int NL>
 __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __restrict__ views,
                                                  const ColInfo* __restrict__ cols,
                                                  const T* __restrict__ padN,
                                                  const T* __restrict__ padT,
                                                  const T* __restrict__ gin, T* __restrict__ out,
                                                  T* __restrict__ rl, double* __restrict__ partials) {
+  static_assert(NL >= 2 && NL <= kZPad + 1 && (RPT > 1 || NL == 2), "level stack");
   __shared__ double red[4];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int r0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * RPT;
   const int view = blockIdx.z;
-  const bool active = c < g.nu && r < g.nv;
   double part = 0.0;
-  if (active) {
+  if (c < g.nu && r0 < g.nv) {
     const ViewInfo vi = views[view];
     const ColInfo ci = cols[(size_t)view * g.nu + c];
     const int nt = vi.step_x ? g.ny : g.nx;
@@ -99,33 +133,50 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
     const int nz = g.nz;
     const int ntp = nt + 1, zs = ns * ntp;
     const T* __restrict__ vb = (vi.step_x ? padT : padN) + pad_index(ns, nt, 0, 0, 0);
-    const float vz = ((float)r - 0.5f * (float)(g.nv - 1)) * g.dvdz;
     const float zc = 0.5f * (float)(nz - 1);
-    int lo, hi;
-    plane_range(ci, vz, zc, nt, nz, lo, hi);
-    float acc0 = 0.f, acc1 = 0.f;
+    float vz[RPT];
+    int lo = ns, hi = -1;  // union of the rows' windows
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      vz[j] = ((float)(r0 + j) - 0.5f * (float)(g.nv - 1)) * g.dvdz;
+      if (r0 + j < g.nv) {
+        int l, h;
+        plane_range(ci, vz[j], zc, nt, nz, l, h);
+        if (l <= h) {
+          lo = min(lo, l);
+          hi = max(hi, h);
+        }
+      }
+    }
+    float acc0[RPT], acc1[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) acc0[j] = acc1[j] = 0.f;
     int p = lo;
     for (; p < hi; p += 2) {
-      acc0 += sample(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs);
-      acc1 += sample(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs);
+      sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+      sample_rows<T, RPT, NL>(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs, acc1);
     }
-    if (p == hi) acc0 += sample(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs);
-    const float acc = acc0 + acc1;
-    const float ell = ray_length(g, vi, ci, r);
-    const size_t o = ((size_t)view * g.nv + r) * g.nu + c;
-    const float val = ell * acc;
-    if (MODE == 0) {
-      st(out + o, val);
-    } else if (MODE == 1) {
-      const float res = ld(gin + o) - val;
-      st(out + o, res);
-      const float rs = ld(out + o);  // the stored (rounded) residual
-      st(rl + o, ell * rs);
-      part = (double)rs * (double)rs;
-    } else {
-      st(out + o, val);
-      const float qs = ld(out + o);
-      part = (double)qs * (double)qs;
+    if (p == hi) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = r0 + j;
+      if (r >= g.nv) break;
+      const float ell = ray_length(g, vi, ci, r);
+      const size_t o = ((size_t)view * g.nv + r) * g.nu + c;
+      const float val = ell * (acc0[j] + acc1[j]);
+      if (MODE == 0) {
+        st(out + o, val);
+      } else if (MODE == 1) {
+        const float res = ld(gin + o) - val;
+        st(out + o, res);
+        const float rs = ld(out + o);  // the stored (rounded) residual
+        st(rl + o, ell * rs);
+        part += (double)rs * (double)rs;
+      } else {
+        st(out + o, val);
+        const float qs = ld(out + o);
+        part += (double)qs * (double)qs;
+      }
     }
   }
   if (MODE != 0) {
@@ -135,26 +186,72 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
   }
 }
 
+// Rows per thread and z levels per plane for a geometry.  On a plane inside
+// the volume the ray parameter is below tau_max = (sad + half-diagonal of
+// the volume grown by two voxels) / sdd (the sample is at most that far from
+// the source, the detector at least sdd), so adjacent rows are less than
+// dv/dz tau_max slices apart; RPT rows then span less than
+// (RPT - 1) dv/dz tau_max slices and need that many levels plus two (with a
+// margin for FP32 rounding).  Of the admissible pairs the one with the
+// fewest loads per sample, NL / RPT, is taken.
+struct RowPlan {
+  int rpt, nl;
+};
+static RowPlan row_plan(const GeomDev& g) {
+  const double hx = (0.5 * g.nx + 2.0) * g.dx, hy = (0.5 * g.ny + 2.0) * g.dy;
+  const double tau_max = ((double)g.sad + std::sqrt(hx * hx + hy * hy)) / (double)g.sdd;
+  const double row_span = (double)g.dvdz * tau_max;
+  const RowPlan cand[] = {{4, 3}, {4, 4}, {2, 3}};
+  for (const RowPlan& c : cand)
+    if (std::ceil((c.rpt - 1) * row_span + 0.05) + 2.0 <= (double)c.nl) return c;
+  return {1, 2};
+}
+
 int project_num_blocks(const GeomDev& g) {
+  // the largest grid of any row plan (one row per thread)
   return ((g.nu + 63) / 64) * ((g.nv + 3) / 4) * g.n_views;
+}
+
+template <typename T, int MODE, int RPT, int NL>
+static void launch_project_rows(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
+                                const T* padN, const T* padT, const T* gin, T* out, T* rl,
+                                double* partials, int* n_partials, hipStream_t s) {
+  dim3 block(256);
+  dim3 grid((g.nu + 63) / 64, (g.nv + 4 * RPT - 1) / (4 * RPT), g.n_views);
+  if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
+  hipLaunchKernelGGL((k_project<T, MODE, RPT, NL>), grid, block, 0, s, g, views, cols, padN, padT,
+                     gin, out, rl, partials);
+}
+
+template <typename T, int MODE>
+static void launch_project_mode(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
+                                const T* padN, const T* padT, const T* gin, T* out, T* rl,
+                                double* partials, int* n_partials, hipStream_t s) {
+  const RowPlan rp = row_plan(g);
+  if (rp.rpt == 4 && rp.nl == 3)
+    launch_project_rows<T, MODE, 4, 3>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
+  else if (rp.rpt == 4)
+    launch_project_rows<T, MODE, 4, 4>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
+  else if (rp.rpt == 2)
+    launch_project_rows<T, MODE, 2, 3>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
+  else
+    launch_project_rows<T, MODE, 1, 2>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
 }
 
 template <typename T>
 hipError_t launch_project(const GeomDev& g, const ViewInfo* views, const ColInfo* cols,
                           const T* padN, const T* padT, int mode, const T* gin, T* out, T* rl,
                           double* partials, int* n_partials, hipStream_t s) {
-  dim3 block(256);
-  dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
-  if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
   if (mode == 0)
-    hipLaunchKernelGGL((k_project<T, 0>), grid, block, 0, s, g, views, cols, padN, padT, gin, out,
-                       rl, partials);
+    launch_project_mode<T, 0>(g, views, cols, padN, padT, gin, out, rl, partials, n_partials, s);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_project<T, 1>), grid, block, 0, s, g, views, cols, padN, padT, gin, out,
-                       rl, partials);
+    launch_project_mode<T, 1>(g, views, cols, padN, padT, gin, out, rl, partials, n_partials, s);
   else
-    hipLaunchKernelGGL((k_project<T, 2>), grid, block, 0, s, g, views, cols, padN, padT, gin, out,
-                       rl, partials);
+    launch_project_mode<T, 2>(g, views, cols, padN, padT, gin, out, rl, partials, n_partials, s);
   return hipGetLastError();
 }
 

@@ -32,17 +32,20 @@ inline size_t dtype_size(tfcb_dtype dt) { return dt == TFCB_F32 ? 4 : 2; }
 
 // ------------------------------------------------------- padded copies
 // The projector reads a volume through zero-padded copies laid out
-// [nz + 2][ns][nt + 1] (one zero slice below and above in z, one zero column
-// after every trans row) behind one leading zero element.  Element (k, p, i)
-// with k in [-1, nz], p in [0, ns), i in [-1, nt] sits at
-// 1 + ((k + 1) ns + p)(nt + 1) + i, so every bilinear tap of a sample with
-// trans index in (-1, nt) and z index in (-1, nz) is inside the buffer and
+// [nz + 2 kZPad][ns][nt + 1] (kZPad zero slices below and above in z, one
+// zero column after every trans row) behind one leading zero element.
+// Element (k, p, i) with k in [-kZPad, nz + kZPad), p in [0, ns), i in
+// [-1, nt] sits at 1 + ((k + kZPad) ns + p)(nt + 1) + i.  A thread that
+// samples several detector rows of one column loads a stack of up to
+// kZPad + 1 consecutive slices per plane; the pads make every such stack of a
+// plane where any of its rows is inside the volume lie inside the buffer, and
 // the taps that fall off the grid read exact zeros: no compares in the loop.
 // "native" copy: ns = ny, nt = nx (y-stepping views); "transposed" copy:
 // ns = nx, nt = ny (x-stepping views).  Only the interior is ever written;
 // the pads are cleared once per call.
+constexpr int kZPad = 3;
 inline size_t pad_elems(int ns, int nt, int nz) {
-  return 1 + (size_t)(nz + 2) * (size_t)ns * (size_t)(nt + 1);
+  return 1 + (size_t)(nz + 2 * kZPad) * (size_t)ns * (size_t)(nt + 1);
 }
 inline size_t pad_elems_vol(int nx, int ny, int nz) {
   // the larger of the two copies' sizes (they differ only in nt + 1)
@@ -50,7 +53,7 @@ inline size_t pad_elems_vol(int nx, int ny, int nz) {
   return a > b ? a : b;
 }
 __host__ __device__ __forceinline__ int pad_index(int ns, int nt, int k, int p, int i) {
-  return 1 + ((k + 1) * ns + p) * (nt + 1) + i;
+  return 1 + ((k + kZPad) * ns + p) * (nt + 1) + i;
 }
 
 // ------------------------------------------------------------- geometry
@@ -168,6 +171,18 @@ hipError_t launch_backproject(const GeomDev& g, const ViewInfo* views, const Col
                               const T* rl, T* vol, double* partials, int* n_partials,
                               hipStream_t s);
 int backproject_num_blocks(const GeomDev& g);
+
+// The paper's operator pair.  Siddon P of the volume given as its native
+// padded copy, modes as launch_project (mode 1 writes no rl).  Eq. (3)
+// backprojection of plain projections (no length prescale); partials as
+// launch_backproject, on the same grid (backproject_num_blocks).
+template <typename T>
+hipError_t launch_project_siddon(const GeomDev& g, const ViewInfo* views, const T* padN, int mode,
+                                 const T* gin, T* out, double* partials, int* n_partials,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_backproject_eq3(const GeomDev& g, const ViewInfo* views, const T* proj, T* vol,
+                                  double* partials, int* n_partials, hipStream_t s);
 
 // rl = l * g for every ray (prescale before P^T).
 template <typename T>

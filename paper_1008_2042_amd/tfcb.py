@@ -23,7 +23,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENUMERIC, EBUSY = 0, -1, -2, -3, -4, 
 EXPORTS = [
     "tfcb_status_str", "tfcb_last_error", "tfcb_version",
     "tfcb_workspace_size", "tfcb_operator_workspace_size", "tfcb_framelet_workspace_size",
-    "tfcb_project", "tfcb_backproject", "tfcb_framelet_shrink", "tfcb_cgls",
+    "tfcb_project", "tfcb_backproject", "tfcb_project_siddon", "tfcb_backproject_eq3",
+    "tfcb_framelet_shrink", "tfcb_cgls",
     "tfcb_restrict_sino", "tfcb_prolong_vol", "tfcb_reconstruct",
     "tfcb_request_bytes", "tfcb_server_create", "tfcb_server_submit", "tfcb_server_step",
     "tfcb_server_poll", "tfcb_server_cancel", "tfcb_server_destroy",
@@ -51,7 +52,8 @@ class Options(ctypes.Structure):
                 ("iters", ctypes.c_int32 * 4), ("cgls_steps", ctypes.c_int32),
                 ("framelet_levels", ctypes.c_int32), ("momentum", ctypes.c_int32),
                 ("positivity", ctypes.c_int32), ("bin_coarse_detector", ctypes.c_int32),
-                ("storage", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("op_pair", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -86,6 +88,8 @@ def load(path: str = LIB_PATH):
         "tfcb_framelet_workspace_size": ([i32, i32, i32, i32, i32, psz], i32),
         "tfcb_project": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_backproject": ([G, i32, vp, vp, vp, sz, vp], i32),
+        "tfcb_project_siddon": ([G, i32, vp, vp, vp, sz, vp], i32),
+        "tfcb_backproject_eq3": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_framelet_shrink": ([i32, i32, i32, i32, dbl, i32, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_cgls": ([G, O, vp, vp, vp, sz, vp, ctypes.POINTER(dbl)], i32),
         "tfcb_restrict_sino": ([G, i32, vp, vp, vp], i32),
@@ -129,11 +133,11 @@ def geometry(g) -> Geometry:
 
 def options(lam: float, iters: Sequence[int], cgls_steps: int = 3, framelet_levels: int = 1,
             momentum: bool = True, positivity: bool = True, bin_detector: bool = True,
-            storage: int = F32, profile: bool = False) -> Options:
+            storage: int = F32, profile: bool = False, op_pair: int = 0) -> Options:
     it = list(iters) + [0] * (4 - len(iters))
     return Options(float(lam), len(iters), (ctypes.c_int32 * 4)(*it), int(cgls_steps),
                    int(framelet_levels), int(bool(momentum)), int(bool(positivity)),
-                   int(bool(bin_detector)), int(storage), int(bool(profile)))
+                   int(bool(bin_detector)), int(storage), int(bool(profile)), int(op_pair))
 
 
 # ---------------------------------------------------------------- torch side
@@ -211,6 +215,32 @@ def backproject(g, proj, out=None, ws=None, stream=None):
     return out
 
 
+def project_siddon(g, vol, out=None, ws=None, stream=None):
+    """proj = P vol by Siddon's ray tracing (the paper's projector)."""
+    torch = _torch()
+    dt = dtype_code(vol.dtype)
+    if out is None:
+        out = torch.empty((g.n_views, g.nv, g.nu), dtype=vol.dtype, device=vol.device)
+    if ws is None:
+        ws = _workspace(operator_workspace_size(g, dt), vol.device)
+    _check(load().tfcb_project_siddon(ctypes.byref(geometry(g)), dt, _ptr(vol), _ptr(out),
+                                      _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
+def backproject_eq3(g, proj, out=None, ws=None, stream=None):
+    """vol = the Eq. (3) closed-form backprojection of proj."""
+    torch = _torch()
+    dt = dtype_code(proj.dtype)
+    if out is None:
+        out = torch.empty((g.nz, g.ny, g.nx), dtype=proj.dtype, device=proj.device)
+    if ws is None:
+        ws = _workspace(operator_workspace_size(g, dt), proj.device)
+    _check(load().tfcb_backproject_eq3(ctypes.byref(geometry(g)), dt, _ptr(proj), _ptr(out),
+                                       _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
 def framelet_shrink(vol, lam: float, levels: int = 1, positivity: bool = True, out=None,
                     stream=None):
     """out = H(W^T T_lambda W vol)."""
@@ -229,10 +259,11 @@ def framelet_shrink(vol, lam: float, levels: int = 1, positivity: bool = True, o
     return out
 
 
-def cgls(g, x, proj, n: int, stream=None):
-    """n CGLS steps from x (updated in place).  Returns (x, resid2, broke)."""
+def cgls(g, x, proj, n: int, stream=None, op_pair: int = 0):
+    """n CGLS steps from x (updated in place), with the Joseph pair or
+    (op_pair 1) the paper's Siddon / Eq. (3) pair.  Returns (x, resid2, broke)."""
     dt = dtype_code(x.dtype)
-    opts = options(0.0, [1], cgls_steps=n, storage=dt)
+    opts = options(0.0, [1], cgls_steps=n, storage=dt, op_pair=op_pair)
     need = workspace_size(g, opts)
     ws = _workspace(need, x.device)
     stats = (ctypes.c_double * 2)()
@@ -261,12 +292,13 @@ def prolong_vol(g_coarse, g_fine, vol, stream=None):
 def reconstruct(g, proj, lam: float, iters: Sequence[int], cgls_steps: int = 3,
                 framelet_levels: int = 1, momentum: bool = True, positivity: bool = True,
                 bin_detector: bool = True, storage: int = F32, out=None, ws=None, stream=None,
-                check: bool = True, profile: bool = False):
+                check: bool = True, profile: bool = False, op_pair: int = 0):
     """The full method on device FP32 projections; returns (volume, report dict).
+    op_pair 1 runs the CGLS with the paper's Siddon / Eq. (3) operators.
     The call synchronises the stream."""
     torch = _torch()
     opts = options(lam, iters, cgls_steps, framelet_levels, momentum, positivity, bin_detector,
-                   storage, profile)
+                   storage, profile, op_pair)
     if out is None:
         out = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=proj.device)
     need = workspace_size(g, opts)

@@ -22,7 +22,7 @@ def test_header_declarations_are_exported():
     lib = _lib()
     with open(os.path.join(ROOT, "include", "tfcb.h")) as fh:
         hdr = fh.read()
-    declared = sorted(set(re.findall(r"\b(tfcb_[a-z_]+)\s*\(", hdr)))
+    declared = sorted(set(re.findall(r"\b(tfcb_[a-z_0-9]+)\s*\(", hdr)))
     assert declared, "no declarations found"
     for name in declared:
         assert hasattr(lib, name), name
@@ -63,6 +63,8 @@ def test_bad_geometry_rejected(field, value):
     # operator calls validate before any device work
     st = lib.tfcb_project(ctypes.byref(cg), 0, 256, 256, 256, 1 << 30, None)
     assert st == tfcb.EINVAL
+    for name in ("tfcb_project_siddon", "tfcb_backproject_eq3"):
+        assert getattr(lib, name)(ctypes.byref(cg), 0, 256, 256, 256, 1 << 30, None) == tfcb.EINVAL
 
 
 def test_bad_options_and_workspace_rejected():
@@ -79,6 +81,12 @@ def test_bad_options_and_workspace_rejected():
             o.n_grids = 5
         assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) \
             == tfcb.EINVAL, kw
+    for pair in (-1, 2):
+        o = tfcb.options(5e-4, [10], op_pair=pair)
+        assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) \
+            == tfcb.EINVAL, pair
+    o = tfcb.options(5e-4, [10], op_pair=1)
+    assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == 0
     o = tfcb.options(5e-4, [10])
     assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == 0
     # too small / misaligned / NULL workspace
