@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16/BF16-storage runs")
+    ap.add_argument("--no-pair", action="store_true",
+                    help="skip the run with the paper's own operators (Siddon P, Eq. (3) P^T)")
     ap.add_argument("--serving", type=int, default=16, metavar="N",
                     help="requests in the serving measurement (0 = skip; 64 = the full mix)")
     ap.add_argument("--workload", default="paper", choices=["paper", "large"],
@@ -173,13 +175,13 @@ def main():
                     "Poisson I0=5e4")
     n_iters = sum(cfg["iters"])
 
-    def run(storage, steps, warmup, profile):
+    def run(storage, steps, warmup, profile, op_pair=0):
         opts = tfcb.options(cfg["lam"], cfg["iters"], cfg["cgls_steps"], cfg["framelet_levels"],
-                            storage=storage, profile=profile)
+                            storage=storage, profile=profile, op_pair=op_pair)
         ws = torch.empty(tfcb.workspace_size(g, opts), dtype=torch.uint8, device=dev)
         out = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)
         kw = dict(cgls_steps=cfg["cgls_steps"], framelet_levels=cfg["framelet_levels"],
-                  storage=storage, out=out, ws=ws)
+                  storage=storage, out=out, ws=ws, op_pair=op_pair)
         for _ in range(warmup):
             tfcb.reconstruct(g, yd, cfg["lam"], cfg["iters"], **kw)
         reps = []
@@ -249,6 +251,21 @@ def main():
                 "value": round(n_iters * args.steps / dth, 3), "unit": "TF iterations/s",
                 "ms_per_step": round(dth / args.steps * 1e3, 3),
                 "rel_l2_vs_f32": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
+    if not args.no_pair:
+        # the paper's own operators in the same schedule (section 2.2.1, Eq. (3))
+        volp, dtp, repp = run(tfcb.F32, args.steps, 1, True, op_pair=1)
+        kp = np.sum([r["kernel_ms"] for r in repp], axis=0)
+        kpn = np.sum([r["kernel_launches"] for r in repp], axis=0)
+        a = volp.double()
+        b = vol32.double()
+        line["config"]["paper_pair"] = {
+            "value": round(n_iters * args.steps / dtp, 3), "unit": "TF iterations/s",
+            "ms_per_step": round(dtp / args.steps * 1e3, 3),
+            "kernel_avg_ms": {n: round(float(kp[i] / kpn[i]) if kpn[i] else 0.0, 4)
+                              for i, n in enumerate(["P (k_project_siddon)",
+                                                     "P^T (k_backproject_eq3)",
+                                                     "framelet (k_framelet)"])},
+            "rel_l2_vs_joseph_pair": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
     if args.serving > 0 and args.workload == "paper":
         from paper_1008_2042_amd import serve
         line["config"]["serving"] = serve.serving_benchmark(n=args.serving, device=dev)
