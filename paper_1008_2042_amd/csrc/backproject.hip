@@ -17,8 +17,9 @@
 // accumulates a run of K voxels along z.  Per view the block first stages
 // its whole detector footprint (the bounding box of the projection of its
 // voxel box grown by one voxel, the support of the hat weights) into LDS
-// with coalesced row loads, so every tap is an LDS read; a view whose
-// footprint does not fit the tile is read from global memory instead.
+// with coalesced row loads, stored column by column so that a column's rows
+// are adjacent, and every tap is an LDS read; a view whose footprint does
+// not fit the tile is read from global memory instead.
 // Within a column the footprint rows are split into z segments (rows whose
 // z index lies between two voxel centres): each row is read once, and the
 // segment sums of g and fr * g give both tent weights.
@@ -37,10 +38,11 @@ constexpr int kTile = 6144;  // LDS floats for one view's staged footprint (24 K
 // [rb, r1].  Segment bounds come from the inverse of the row map; a row
 // misplaced by rounding at a bound has fr within an ulp of 0 or 1, so its
 // weights are still right.  Within a segment fr grows by zstep = tau dv/dz
-// per row, so with the first row's fraction f_b (the projector's
-// expression) only sum g and sum (r - r_b) g are accumulated:
-// sum fr g = f_b sum g + zstep sum (r - r_b) g.  Each segment is added to
-// its two voxels as soon as it is complete.
+// per row from the first row's fraction f_b (the projector's expression), so
+// sum fr g = f_b S + zstep sum_i i g_i over the segment's rows i = 0..n-1,
+// with S = sum g.  The second sum comes from two running sums (T += S before
+// each S += g gives T = sum (n - 1 - i) g_i, so sum i g_i = (n - 1) S - T).
+// Each segment is added to its two voxels as soon as it is complete.
 template <int K, typename P>
 __device__ __forceinline__ void column_to_run(const P* __restrict__ col, int stride, int row0,
                                               int r1, int rb, int k0, float tau, float zstep,
@@ -55,26 +57,25 @@ __device__ __forceinline__ void column_to_run(const P* __restrict__ col, int str
     // of the row loops (which would hold them in registers)
     asm volatile("" : "+v"(base));
     const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
-    float a0 = 0.f, a1 = 0.f, fo = 0.f;
-    const P* __restrict__ gp = col + (size_t)(rb - row0) * stride;
-    int r = rb;
-    for (; r + 1 < re; r += 2) {
+    const int n = re - rb;
+    float S = 0.f, T = 0.f;
+    const P* __restrict__ gp = col + (rb - row0) * stride;
+    int i = 0;
+    for (; i + 1 < n; i += 2) {
       const float g0 = ld(gp), g1 = ld(gp + stride);
       gp += 2 * stride;
-      a0 += g0;
-      a1 = fmaf(fo, g0, a1);
-      a0 += g1;
-      a1 = fmaf(fo + 1.f, g1, a1);
-      fo += 2.f;
+      T += S;
+      S += g0;
+      T += S;
+      S += g1;
     }
-    if (r < re) {
-      const float g0 = ld(gp);
-      a0 += g0;
-      a1 = fmaf(fo, g0, a1);
+    if (i < n) {
+      T += S;
+      S += ld(gp);
     }
     const float fb = fmaf(tau, vz_tab[min(rb, nv - 1)], zc) - base;
-    const float s1 = fmaf(fb, a0, zstep * a1);  // sum fr g
-    if (m > 0) acc[m - 1] = fmaf(wt, a0 - s1, acc[m - 1]);
+    const float s1 = fmaf(fb, S, zstep * fmaf((float)(n - 1), S, -T));  // sum fr g
+    if (m > 0) acc[m - 1] = fmaf(wt, S - s1, acc[m - 1]);
     if (m < K) acc[m] = fmaf(wt, s1, acc[m]);
     rb = re;
     base += 1.f;
@@ -143,7 +144,10 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
     const int c0 = max(0, (int)floorf(umin) - 1), c1 = min(g.nu - 1, (int)ceilf(umax) + 1);
     const int r0 = max(0, (int)floorf(vmin) - 1), r1 = min(g.nv - 1, (int)ceilf(vmax) + 1);
     const int W = c1 - c0 + 1, H = r1 - r0 + 1;
-    const bool staged = W > 0 && H > 0 && W * H <= kTile;
+    // column-major tile, odd column stride: a column's rows are adjacent
+    // (two per LDS read) and adjacent columns fall in different banks
+    const int Hs = H | 1;
+    const bool staged = W > 0 && H > 0 && W * Hs <= kTile;
     if (staged) {
       // each wave takes rows wave, wave + 4, ...; a lane loads 4 rows x 2
       // columns before it writes any, so 8 loads per lane are in flight
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
               const int row = rr + 4 * u, cc = cb + lane + 64 * h;
-              if (row < H && cc < W) tile[row * W + cc] = v[u][h];
+              if (row < H && cc < W) tile[cc * Hs + row] = v[u][h];
             }
         }
       }
@@ -189,16 +193,17 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
       Xb = X + g.dx;
     }
     // detector column of a point: u = sdd (-x sn + y cs) / (sad - (x cs + y sn));
-    // the columns are only bracketed (one column of slack each side), so the
-    // hardware reciprocal is accurate enough
+    // the hardware reciprocal is accurate to ~1e-4 column here
     const float ua = g.sdd * (-Xa * vi.sn + Ya * vi.cs) *
                      __builtin_amdgcn_rcpf(g.sad - (Xa * vi.cs + Ya * vi.sn));
     const float ub = g.sdd * (-Xb * vi.sn + Yb * vi.cs) *
                      __builtin_amdgcn_rcpf(g.sad - (Xb * vi.cs + Yb * vi.sn));
     const float ca = fmaf(ua, inv_du, cu), cb = fmaf(ub, inv_du, cu);
-    // every column with a non-zero weight lies inside the footprint box
-    const int clo = max(c0, (int)floorf(fminf(ca, cb)));
-    const int chi = min(c1, (int)ceilf(fmaxf(ca, cb)));
+    // a column has a non-zero trans weight only strictly between ca and cb
+    // (the margin covers the reciprocal's error); all of them lie inside
+    // the footprint box
+    const int clo = max(c0, (int)floorf(fminf(ca, cb) - 1e-3f) + 1);
+    const int chi = min(c1, (int)ceilf(fmaxf(ca, cb) + 1e-3f) - 1);
     const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
     const float fp = (float)p;
     for (int c = clo; c <= chi; ++c) {
@@ -216,8 +221,8 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
       const float inv_s = __builtin_amdgcn_rcpf(zstep);
       const int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
       if (staged)
-        column_to_run<K>(tile + (c - c0), W, r0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
-                         g.nv, acc);
+        column_to_run<K>(tile + (c - c0) * Hs, 1, r0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt,
+                         vz_tab, g.nv, acc);
       else
         column_to_run<K>(rview + c, g.nu, 0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
                          g.nv, acc);

@@ -286,7 +286,7 @@ template <typename T>
 hipError_t pair_project(const GridBufs& b, const T* pN, const T* pT, int mode, const T* gin,
                         T* out, T* rl, int* np, hipStream_t s) {
   if (b.op_pair == 1)
-    return launch_project_siddon(b.gd, b.views, pN, mode, gin, out, b.partials, np, s);
+    return launch_project_siddon(b.gd, b.views, pN, pT, mode, gin, out, b.partials, np, s);
   return launch_project(b.gd, b.views, b.cols, pN, pT, mode, gin, out, rl, b.partials, np, s);
 }
 template <typename T>

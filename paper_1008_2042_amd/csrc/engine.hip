@@ -112,8 +112,8 @@ tfcb_status tfcb_backproject(const tfcb_geometry* g, tfcb_dtype dt, const void* 
   });
 }
 
-// Siddon P (section 2.2.1) of a native volume: its native padded copy is
-// built in the operator workspace, where tfcb_project keeps it too.
+// Siddon P (section 2.2.1) of a native volume: its padded copies are built
+// in the operator workspace, where tfcb_project keeps them too.
 tfcb_status tfcb_project_siddon(const tfcb_geometry* g, tfcb_dtype dt, const void* vol,
                                 void* proj, void* ws, size_t ws_bytes, void* stream) {
   TFCB_TRY(validate_geometry(g));
@@ -136,9 +136,11 @@ tfcb_status tfcb_project_siddon(const tfcb_geometry* g, tfcb_dtype dt, const voi
     TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
     const GeomDev gd = make_geom_dev(*g);
     TFCB_HIP(launch_fill(nN, 0.f, padN, s));
+    TFCB_HIP(launch_fill(nT, 0.f, padT, s));
     TFCB_HIP(launch_pad_copies(g->nx, g->ny, g->nz, static_cast<const T*>(vol), padN, padT, s));
-    TFCB_HIP(launch_project_siddon(gd, views, (const T*)padN, 0, static_cast<const T*>(nullptr),
-                                   static_cast<T*>(proj), nullptr, nullptr, s));
+    TFCB_HIP(launch_project_siddon(gd, views, (const T*)padN, (const T*)padT, 0,
+                                   static_cast<const T*>(nullptr), static_cast<T*>(proj), nullptr,
+                                   nullptr, s));
     return TFCB_OK;
   });
 }

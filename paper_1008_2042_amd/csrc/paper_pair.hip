@@ -13,8 +13,8 @@
 // on.  Every face parameter of an axis comes from one expression,
 // (face position - source) / a, also for the ray's entry and exit, so the
 // walk never leaves the volume and ends after at most nx + ny + nz + 3
-// steps.  It reads the native zero-padded copy of the volume that the CGLS
-// keeps for P.
+// steps.  It reads the zero-padded volume copies that the CGLS keeps for P
+// (the one whose fastest axis is the view's trans axis).
 //
 // Eq. (3) P^T: one thread per z-run of K voxels of one (x, y) column; per
 // view the in-plane part of the projection (magnification, detector column
@@ -83,6 +83,7 @@ __device__ __forceinline__ int faces_before(const SiddonAxis& ax, float a, float
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_project_siddon(GeomDev g, const ViewInfo* __restrict__ views,
                                                         const T* __restrict__ padN,
+                                                        const T* __restrict__ padT,
                                                         const T* __restrict__ gin,
                                                         T* __restrict__ out,
                                                         double* __restrict__ partials) {
@@ -141,11 +142,27 @@ __global__ __launch_bounds__(256) void k_project_siddon(GeomDev g, const ViewInf
         iz = Z.dir > 0 ? bz - 1 : bz;
         nza = face_alpha(Z, bz);
       }
-      // offsets in the native padded copy [nz + 2 kZPad][ny][nx + 1]
-      const int rowp = g.nx + 1, slab = g.ny * rowp;
-      const T* __restrict__ vb = padN + pad_index(g.ny, g.nx, 0, 0, 0);
-      int o = (iz * g.ny + iy) * rowp + ix;
-      const int ox = X.dir, oy = Y.dir * rowp, oz = Z.dir * slab;
+      // Offsets in a padded copy: views stepping along y read the native
+      // copy [nz + 2 kZPad][ny][nx + 1], those stepping along x the
+      // transposed one [nz + 2 kZPad][nx][ny + 1], so that adjacent detector
+      // columns (lanes) walk adjacent addresses of the fastest axis.
+      const T* __restrict__ vb;
+      int o, ox, oy, oz;
+      if (vi.step_x) {
+        const int rowp = g.ny + 1, slab = g.nx * rowp;
+        vb = padT + pad_index(g.nx, g.ny, 0, 0, 0);
+        o = (iz * g.nx + ix) * rowp + iy;
+        ox = X.dir * rowp;
+        oy = Y.dir;
+        oz = Z.dir * slab;
+      } else {
+        const int rowp = g.nx + 1, slab = g.ny * rowp;
+        vb = padN + pad_index(g.ny, g.nx, 0, 0, 0);
+        o = (iz * g.ny + iy) * rowp + ix;
+        ox = X.dir;
+        oy = Y.dir * rowp;
+        oz = Z.dir * slab;
+      }
       float alpha = amin;
       // every step moves at least one axis past a face or reaches amax, and
       // an axis passes at most n + 1 faces: at most nx + ny + nz + 3 steps
@@ -193,21 +210,21 @@ __global__ __launch_bounds__(256) void k_project_siddon(GeomDev g, const ViewInf
 }
 
 template <typename T>
-hipError_t launch_project_siddon(const GeomDev& g, const ViewInfo* views, const T* padN, int mode,
-                                 const T* gin, T* out, double* partials, int* n_partials,
-                                 hipStream_t s) {
+hipError_t launch_project_siddon(const GeomDev& g, const ViewInfo* views, const T* padN,
+                                 const T* padT, int mode, const T* gin, T* out, double* partials,
+                                 int* n_partials, hipStream_t s) {
   dim3 block(256);
   dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
   if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
   if (mode == 0)
-    hipLaunchKernelGGL((k_project_siddon<T, 0>), grid, block, 0, s, g, views, padN, gin, out,
-                       partials);
+    hipLaunchKernelGGL((k_project_siddon<T, 0>), grid, block, 0, s, g, views, padN, padT, gin,
+                       out, partials);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_project_siddon<T, 1>), grid, block, 0, s, g, views, padN, gin, out,
-                       partials);
+    hipLaunchKernelGGL((k_project_siddon<T, 1>), grid, block, 0, s, g, views, padN, padT, gin,
+                       out, partials);
   else
-    hipLaunchKernelGGL((k_project_siddon<T, 2>), grid, block, 0, s, g, views, padN, gin, out,
-                       partials);
+    hipLaunchKernelGGL((k_project_siddon<T, 2>), grid, block, 0, s, g, views, padN, padT, gin,
+                       out, partials);
   return hipGetLastError();
 }
 
@@ -312,8 +329,8 @@ hipError_t launch_backproject_eq3(const GeomDev& g, const ViewInfo* views, const
 }
 
 #define TFCB_INST(T)                                                                              \
-  template hipError_t launch_project_siddon<T>(const GeomDev&, const ViewInfo*, const T*, int,     \
-                                               const T*, T*, double*, int*, hipStream_t);          \
+  template hipError_t launch_project_siddon<T>(const GeomDev&, const ViewInfo*, const T*, const T*, \
+                                               int, const T*, T*, double*, int*, hipStream_t);     \
   template hipError_t launch_backproject_eq3<T>(const GeomDev&, const ViewInfo*, const T*, T*,     \
                                                 double*, int*, hipStream_t);
 TFCB_INST(float)

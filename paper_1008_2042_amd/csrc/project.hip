@@ -151,12 +151,20 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
     float acc0[RPT], acc1[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) acc0[j] = acc1[j] = 0.f;
-    int p = lo;
-    for (; p < hi; p += 2) {
-      sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
-      sample_rows<T, RPT, NL>(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs, acc1);
+    if (RPT >= 8) {
+      // one plane per iteration: NL loads in flight already, and half the
+      // registers of two planes
+      for (int p = lo; p <= hi; ++p)
+        sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+    } else {
+      // two planes per iteration (even planes into acc0, odd into acc1)
+      int p = lo;
+      for (; p < hi; p += 2) {
+        sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+        sample_rows<T, RPT, NL>(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs, acc1);
+      }
+      if (p == hi) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
     }
-    if (p == hi) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int r = r0 + j;
@@ -201,7 +209,7 @@ static RowPlan row_plan(const GeomDev& g) {
   const double hx = (0.5 * g.nx + 2.0) * g.dx, hy = (0.5 * g.ny + 2.0) * g.dy;
   const double tau_max = ((double)g.sad + std::sqrt(hx * hx + hy * hy)) / (double)g.sdd;
   const double row_span = (double)g.dvdz * tau_max;
-  const RowPlan cand[] = {{4, 3}, {4, 4}, {2, 3}};
+  const RowPlan cand[] = {{16, 6}, {8, 4}, {8, 6}, {4, 3}, {4, 4}, {2, 3}};
   for (const RowPlan& c : cand)
     if (std::ceil((c.rpt - 1) * row_span + 0.05) + 2.0 <= (double)c.nl) return c;
   return {1, 2};
@@ -228,7 +236,16 @@ static void launch_project_mode(const GeomDev& g, const ViewInfo* views, const C
                                 const T* padN, const T* padT, const T* gin, T* out, T* rl,
                                 double* partials, int* n_partials, hipStream_t s) {
   const RowPlan rp = row_plan(g);
-  if (rp.rpt == 4 && rp.nl == 3)
+  if (rp.rpt == 16)
+    launch_project_rows<T, MODE, 16, 6>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                        n_partials, s);
+  else if (rp.rpt == 8 && rp.nl == 4)
+    launch_project_rows<T, MODE, 8, 4>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
+  else if (rp.rpt == 8)
+    launch_project_rows<T, MODE, 8, 6>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
+  else if (rp.rpt == 4 && rp.nl == 3)
     launch_project_rows<T, MODE, 4, 3>(g, views, cols, padN, padT, gin, out, rl, partials,
                                        n_partials, s);
   else if (rp.rpt == 4)

@@ -43,7 +43,7 @@ inline size_t dtype_size(tfcb_dtype dt) { return dt == TFCB_F32 ? 4 : 2; }
 // "native" copy: ns = ny, nt = nx (y-stepping views); "transposed" copy:
 // ns = nx, nt = ny (x-stepping views).  Only the interior is ever written;
 // the pads are cleared once per call.
-constexpr int kZPad = 3;
+constexpr int kZPad = 5;
 inline size_t pad_elems(int ns, int nt, int nz) {
   return 1 + (size_t)(nz + 2 * kZPad) * (size_t)ns * (size_t)(nt + 1);
 }
@@ -172,14 +172,14 @@ hipError_t launch_backproject(const GeomDev& g, const ViewInfo* views, const Col
                               hipStream_t s);
 int backproject_num_blocks(const GeomDev& g);
 
-// The paper's operator pair.  Siddon P of the volume given as its native
-// padded copy, modes as launch_project (mode 1 writes no rl).  Eq. (3)
+// The paper's operator pair.  Siddon P of the volume given as its two
+// padded copies, modes as launch_project (mode 1 writes no rl).  Eq. (3)
 // backprojection of plain projections (no length prescale); partials as
 // launch_backproject, on the same grid (backproject_num_blocks).
 template <typename T>
-hipError_t launch_project_siddon(const GeomDev& g, const ViewInfo* views, const T* padN, int mode,
-                                 const T* gin, T* out, double* partials, int* n_partials,
-                                 hipStream_t s);
+hipError_t launch_project_siddon(const GeomDev& g, const ViewInfo* views, const T* padN,
+                                 const T* padT, int mode, const T* gin, T* out, double* partials,
+                                 int* n_partials, hipStream_t s);
 template <typename T>
 hipError_t launch_backproject_eq3(const GeomDev& g, const ViewInfo* views, const T* proj, T* vol,
                                   double* partials, int* n_partials, hipStream_t s);
