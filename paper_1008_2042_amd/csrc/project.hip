@@ -11,7 +11,8 @@
 // apart, so one thread loads a stack of NL consecutive z levels of the plane
 // (one 8-byte load of the two trans taps per level), interpolates each level
 // in trans once, and takes every row's bilinear sample from the two levels
-// around it.  RPT = 1 (NL = 2) is the one-ray-per-thread kernel.
+// around it.  RPT = 1 (NL = 2) is the one-ray-per-thread kernel.  PU planes
+// per iteration, alternating between two accumulator sets.
 #include <cmath>
 
 #include "tfcb_internal.h"
@@ -112,7 +113,7 @@ __device__ __forceinline__ void sample_rows(const T* __restrict__ vb, const ColI
   }
 }
 
-template <typename T, int MODE, int RPT, int NL>
+template <typename T, int MODE, int RPT, int NL, int PU = 2>
 __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __restrict__ views,
                                                  const ColInfo* __restrict__ cols,
                                                  const T* __restrict__ padN,
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
                                                  const T* __restrict__ gin, T* __restrict__ out,
                                                  T* __restrict__ rl, double* __restrict__ partials) {
   static_assert(NL >= 2 && NL <= kZPad + 1 && (RPT > 1 || NL == 2), "level stack");
+  static_assert(PU >= 2 && PU % 2 == 0, "planes per iteration");
   __shared__ double red[4];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
   const int r0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * RPT;
@@ -148,23 +150,19 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
         }
       }
     }
+    // PU planes per iteration, alternate planes into two accumulator sets
     float acc0[RPT], acc1[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) acc0[j] = acc1[j] = 0.f;
-    if (RPT >= 8) {
-      // one plane per iteration: NL loads in flight already, and half the
-      // registers of two planes
-      for (int p = lo; p <= hi; ++p)
-        sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
-    } else {
-      // two planes per iteration (even planes into acc0, odd into acc1)
-      int p = lo;
-      for (; p < hi; p += 2) {
-        sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
-        sample_rows<T, RPT, NL>(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs, acc1);
+    int p = lo;
+    for (; p + PU - 1 <= hi; p += PU) {
+#pragma unroll
+      for (int u = 0; u < PU; u += 2) {
+        sample_rows<T, RPT, NL>(vb, ci, p + u, vz, zc, nt, nz, ns, ntp, zs, acc0);
+        sample_rows<T, RPT, NL>(vb, ci, p + u + 1, vz, zc, nt, nz, ns, ntp, zs, acc1);
       }
-      if (p == hi) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
     }
+    for (; p <= hi; ++p) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int r = r0 + j;
