@@ -75,7 +75,7 @@ tfcb_status validate_geometry(const tfcb_geometry* g) {
     return fail(TFCB_EUNSUPPORTED, "an axis exceeds 65535");
   if (g->nv > 16384 || g->nu > 65535)
     return fail(TFCB_EUNSUPPORTED, "detector larger than 65535 x 16384 pixels");
-  const double pad = (double)(g->nz + 2 * kZPad) * std::max(g->nx, g->ny) * (std::max(g->nx, g->ny) + 1);
+  const double pad = (double)(g->nz + 2 * kZPad) * std::max(g->nx, g->ny) * (std::max(g->nx, g->ny) + 4) + 8;
   if (pad >= 2147483647.0)
     return fail(TFCB_EUNSUPPORTED, "padded volume copy exceeds 2^31 elements");
   if (g->angles)

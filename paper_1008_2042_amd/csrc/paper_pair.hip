@@ -143,20 +143,20 @@ __global__ __launch_bounds__(256) void k_project_siddon(GeomDev g, const ViewInf
         nza = face_alpha(Z, bz);
       }
       // Offsets in a padded copy: views stepping along y read the native
-      // copy [nz + 2 kZPad][ny][nx + 1], those stepping along x the
-      // transposed one [nz + 2 kZPad][nx][ny + 1], so that adjacent detector
+      // copy [nz + 2 kZPad][ny][pad_row(nx)], those stepping along x the
+      // transposed one [nz + 2 kZPad][nx][pad_row(ny)], so that adjacent detector
       // columns (lanes) walk adjacent addresses of the fastest axis.
       const T* __restrict__ vb;
       int o, ox, oy, oz;
       if (vi.step_x) {
-        const int rowp = g.ny + 1, slab = g.nx * rowp;
+        const int rowp = pad_row(g.ny), slab = g.nx * rowp;
         vb = padT + pad_index(g.nx, g.ny, 0, 0, 0);
         o = (iz * g.nx + ix) * rowp + iy;
         ox = X.dir * rowp;
         oy = Y.dir;
         oz = Z.dir * slab;
       } else {
-        const int rowp = g.nx + 1, slab = g.ny * rowp;
+        const int rowp = pad_row(g.nx), slab = g.ny * rowp;
         vb = padN + pad_index(g.ny, g.nx, 0, 0, 0);
         o = (iz * g.ny + iy) * rowp + ix;
         ox = X.dir;

@@ -63,6 +63,27 @@ __device__ __forceinline__ void plane_range(const ColInfo& ci, float vz, float z
   while (hi >= lo && !sample_inside(ci, hi, vz, zc, nt, nz)) --hi;
 }
 
+// Row j's bilinear sample from the trans-interpolated levels: the two levels
+// around its z index, d_j = floor(zh_j) - floor(zh_0) and d_j + 1.  The
+// rows' z indices rise with j by less than one slice per row, so d_j is
+// d_{j-1} or d_{j-1} + 1: the pair is carried along as a shift register of
+// the levels, which moves on where floor(zh_j) exceeds floor(zh_{j-1}).
+template <int RPT, int NL>
+__device__ __forceinline__ void rows_from_levels(const float (&lev)[NL], const float (&zh)[RPT],
+                                                 const float (&zf)[RPT], float (&acc)[RPT]) {
+  float win[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) win[l] = lev[l];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    if (j > 0 && zf[j] > zf[j - 1]) {
+#pragma unroll
+      for (int l = 0; l + 1 < NL; ++l) win[l] = win[l + 1];
+    }
+    acc[j] += fmaf(zh[j] - zf[j], win[1] - win[0], win[0]);
+  }
+}
+
 // The samples of plane p for the RPT rows of one column (row j's z factor
 // vz[j], increasing in j).  The padded copy `vb` points at element
 // (0, 0, 0); trans stride 1, plane stride ntp, z stride zs.
@@ -97,20 +118,7 @@ __device__ __forceinline__ void sample_rows(const T* __restrict__ vb, const ColI
     const float v0 = ld(q + l * zs), v1 = ld(q + l * zs + 1);
     lev[l] = fmaf(wt, v1 - v0, v0);
   }
-#pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    float lo = lev[0], up = lev[1];
-    if (j > 0) {
-      const int d = (int)zf[j] - iz0;
-#pragma unroll
-      for (int l = 1; l < NL - 1; ++l)
-        if (d >= l) {
-          lo = lev[l];
-          up = lev[l + 1];
-        }
-    }
-    acc[j] += fmaf(zh[j] - zf[j], up - lo, lo);
-  }
+  rows_from_levels<RPT, NL>(lev, zh, zf, acc);
 }
 
 template <typename T, int MODE, int RPT, int NL, int PU = 2>
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
     const int nt = vi.step_x ? g.ny : g.nx;
     const int ns = vi.step_x ? g.nx : g.ny;
     const int nz = g.nz;
-    const int ntp = nt + 1, zs = ns * ntp;
+    const int ntp = pad_row(nt), zs = ns * ntp;
     const T* __restrict__ vb = (vi.step_x ? padT : padN) + pad_index(ns, nt, 0, 0, 0);
     const float zc = 0.5f * (float)(nz - 1);
     float vz[RPT];
@@ -163,6 +171,284 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
       }
     }
     for (; p <= hi; ++p) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = r0 + j;
+      if (r >= g.nv) break;
+      const float ell = ray_length(g, vi, ci, r);
+      const size_t o = ((size_t)view * g.nv + r) * g.nu + c;
+      const float val = ell * (acc0[j] + acc1[j]);
+      if (MODE == 0) {
+        st(out + o, val);
+      } else if (MODE == 1) {
+        const float res = ld(gin + o) - val;
+        st(out + o, res);
+        const float rs = ld(out + o);  // the stored (rounded) residual
+        st(rl + o, ell * rs);
+        part += (double)rs * (double)rs;
+      } else {
+        st(out + o, val);
+        const float qs = ld(out + o);
+        part += (double)qs * (double)qs;
+      }
+    }
+  }
+  if (MODE != 0) {
+    const double s = wave_block_sum(part, red);
+    if (threadIdx.x == 0)
+      partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------- staged P
+// The same samples, with each plane's volume data staged in LDS per block.
+// A block (64 columns x 4 RPT rows) walks the union of its threads' plane
+// windows.  For every plane the box of levels and trans positions its
+// threads can touch follows from the block's corner rays (the trans index is
+// monotone in the column, the z index in the column and the row), widened by
+// 0.01 for rounding: z levels from the lowest row's floor to the stack top of
+// the last wave's first row, trans positions from the lower corner's floor
+// down to a 4-element boundary up to the upper corner's floor + 1.  The box's
+// level rows are loaded with aligned 4-element vector loads (each needed
+// line once per block and plane) into one of two LDS buffers while the
+// threads sample the other one, so a plane costs one barrier.  A block whose
+// box can exceed the buffers on any of its planes takes the direct path of
+// k_project instead.
+constexpr int kStageF4 = 32;    // 4-element vectors per staged level row
+constexpr int kStageRows = 24;  // level rows per staged plane
+constexpr int kStageRegs = (kStageRows * kStageF4 + 255) / 256;
+constexpr int kStageBoxes = 1024;  // planes whose boxes a block tabulates in LDS
+
+template <typename T> __device__ __forceinline__ float4 ld4(const T* p);
+template <> __device__ __forceinline__ float4 ld4<float>(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p) {
+  const uint2 u = *reinterpret_cast<const uint2*>(p);
+  __half_raw h0, h1, h2, h3;
+  h0.x = (unsigned short)(u.x & 0xffffu);
+  h1.x = (unsigned short)(u.x >> 16);
+  h2.x = (unsigned short)(u.y & 0xffffu);
+  h3.x = (unsigned short)(u.y >> 16);
+  return make_float4(__half2float(__half(h0)), __half2float(__half(h1)),
+                     __half2float(__half(h2)), __half2float(__half(h3)));
+}
+template <> __device__ __forceinline__ float4 ld4<__hip_bfloat16>(const __hip_bfloat16* p) {
+  // a bfloat16 is the upper half of the float with the same bits
+  const uint2 u = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                     __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+}
+
+struct StageBox {
+  int zl, nzr;  // first level row and level-row count
+  int tl4, nf4; // first trans element (a multiple of 4) and vector count
+};
+
+__device__ __forceinline__ StageBox stage_box(const ColInfo& cA, const ColInfo& cB, float vzA,
+                                              float vzB, int p, float zc, int nt, int nz, int nl) {
+  const float tA = trans_index(cA, p), tB = trans_index(cB, p);
+  const int tlo = max((int)floorf(fminf(tA, tB) - 0.01f), -1);
+  const int thi = min((int)floorf(fmaxf(tA, tB) + 0.01f) + 1, nt);
+  const float z1 = z_index(cA, p, vzA, zc), z2 = z_index(cB, p, vzA, zc);
+  const float z3 = z_index(cA, p, vzB, zc), z4 = z_index(cB, p, vzB, zc);
+  StageBox b;
+  b.zl = max((int)floorf(fminf(z1, z2) - 0.01f), -kZPad);
+  const int ztop = min((int)floorf(fmaxf(z3, z4) + 0.01f), nz - 1) + nl - 1;
+  b.nzr = max(ztop - b.zl + 1, 0);
+  b.tl4 = tlo & ~3;
+  b.nf4 = thi >= tlo ? ((thi - b.tl4) >> 2) + 1 : 0;
+  return b;
+}
+
+// The samples of plane p for the RPT rows of one column, from the staged box
+// `tile` (level row z - b.zl, element i - b.tl4, rows of 4 kStageF4).  Same
+// arithmetic as sample_rows.
+template <int RPT, int NL>
+__device__ __forceinline__ void sample_rows_lds(const float* __restrict__ tile, const StageBox& b,
+                                                const ColInfo& ci, int p, const float (&vz)[RPT],
+                                                float zc, int nt, int nz, float (&acc)[RPT]) {
+  const float th = trans_index(ci, p);
+  const float tf = floorf(th);
+  const int it = min(max((int)tf, -1), nt - 1);
+  const float wt = th - tf;
+  float zh[RPT], zf[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    zh[j] = z_index(ci, p, vz[j], zc);
+    zf[j] = floorf(zh[j]);
+  }
+  const int iz0 = min(max((int)zf[0], -kZPad), nz - 1);
+  const float* __restrict__ q = tile + (iz0 - b.zl) * (4 * kStageF4) + (it - b.tl4);
+  float lev[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const float v0 = q[l * 4 * kStageF4], v1 = q[l * 4 * kStageF4 + 1];
+    lev[l] = fmaf(wt, v1 - v0, v0);
+  }
+  rows_from_levels<RPT, NL>(lev, zh, zf, acc);
+}
+
+template <typename T, int MODE, int RPT, int NL>
+__global__ __launch_bounds__(256) void k_project_staged(GeomDev g, const ViewInfo* __restrict__ views,
+                                                        const ColInfo* __restrict__ cols,
+                                                        const T* __restrict__ padN,
+                                                        const T* __restrict__ padT,
+                                                        const T* __restrict__ gin,
+                                                        T* __restrict__ out, T* __restrict__ rl,
+                                                        double* __restrict__ partials) {
+  static_assert(NL >= 2 && NL <= kZPad + 1 && RPT > 1, "level stack");
+  __shared__ double red[4];
+  __shared__ int srange[8];
+  __shared__ float4 tile[2][kStageRows * kStageF4];
+  __shared__ int4 boxes[kStageBoxes];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cblk = blockIdx.x * 64, rblk = blockIdx.y * 4 * RPT;
+  const int c = cblk + lane;
+  const int r0 = rblk + wave * RPT;
+  const int view = blockIdx.z;
+  const ViewInfo vi = views[view];
+  const int nt = vi.step_x ? g.ny : g.nx;
+  const int ns = vi.step_x ? g.nx : g.ny;
+  const int nz = g.nz;
+  const T* __restrict__ base = vi.step_x ? padT : padN;
+  const float zc = 0.5f * (float)(nz - 1);
+  const bool active = c < g.nu && r0 < g.nv;
+  const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
+  const ColInfo ci = cview[min(c, g.nu - 1)];
+  float vz[RPT];
+  int lo = ns, hi = -1;  // union of the rows' windows
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    vz[j] = ((float)(r0 + j) - 0.5f * (float)(g.nv - 1)) * g.dvdz;
+    if (active && r0 + j < g.nv) {
+      int l, h;
+      plane_range(ci, vz[j], zc, nt, nz, l, h);
+      if (l <= h) {
+        lo = min(lo, l);
+        hi = max(hi, h);
+      }
+    }
+  }
+  // the block's plane range
+  int mlo = lo, mhi = hi;
+  for (int off = 32; off > 0; off >>= 1) {
+    mlo = min(mlo, __shfl_xor(mlo, off, 64));
+    mhi = max(mhi, __shfl_xor(mhi, off, 64));
+  }
+  if (lane == 0) {
+    srange[wave] = mlo;
+    srange[4 + wave] = mhi;
+  }
+  __syncthreads();
+  const int LO = min(min(srange[0], srange[1]), min(srange[2], srange[3]));
+  const int HI = max(max(srange[4], srange[5]), max(srange[6], srange[7]));
+  // corner rays: the block's first and last column, its first row and the
+  // first row of its last wave
+  const ColInfo cA = cview[cblk], cB = cview[min(cblk + 63, g.nu - 1)];
+  const float vzA = ((float)rblk - 0.5f * (float)(g.nv - 1)) * g.dvdz;
+  const float vzB = ((float)min(rblk + 3 * RPT, g.nv - 1) - 0.5f * (float)(g.nv - 1)) * g.dvdz;
+  bool staged = LO <= HI;
+  if (staged) {
+    // Bounds of the box over all planes: the z span between the corner rays
+    // (max of two linear functions minus min of two) and the trans width
+    // |tB - tA| are convex in p, so their largest values over [LO, HI] are
+    // at the ends; the floors, the 0.01 widenings, the stack height and the
+    // 4-element alignment add at most the constants below.
+    float span = 0.f, width = 0.f;
+    for (int e = 0; e < 2; ++e) {
+      const int pe = e ? HI : LO;
+      const float z1 = z_index(cA, pe, vzA, zc), z2 = z_index(cB, pe, vzA, zc);
+      const float z3 = z_index(cA, pe, vzB, zc), z4 = z_index(cB, pe, vzB, zc);
+      span = fmaxf(span, fmaxf(z3, z4) - fminf(z1, z2));
+      width = fmaxf(width, fabsf(trans_index(cB, pe) - trans_index(cA, pe)));
+    }
+    const int max_rows = (int)floorf(span + 0.02f) + NL + 1;
+    const int max_f4 = (((int)floorf(width + 0.02f) + 5) >> 2) + 1;
+    staged = max_rows <= kStageRows && max_f4 <= kStageF4;
+  }
+  float acc0[RPT], acc1[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) acc0[j] = acc1[j] = 0.f;
+  if (staged) {
+    // the boxes of all the block's planes, computed once (up to
+    // kStageBoxes planes; beyond that each thread computes them itself)
+    const bool table = HI - LO < kStageBoxes;
+    if (table)
+      for (int i = threadIdx.x; i <= HI - LO; i += 256) {
+        const StageBox b = stage_box(cA, cB, vzA, vzB, LO + i, zc, nt, nz, NL);
+        boxes[i] = make_int4(b.zl, b.nzr, b.tl4, b.nf4);
+      }
+    __syncthreads();
+    auto get_box = [&](int p) {
+      StageBox b;
+      if (table) {
+        const int4 v = boxes[p - LO];
+        b.zl = v.x;
+        b.nzr = v.y;
+        b.tl4 = v.z;
+        b.nf4 = v.w;
+      } else {
+        b = stage_box(cA, cB, vzA, vzB, p, zc, nt, nz, NL);
+      }
+      return b;
+    };
+    float4 reg[kStageRegs];
+    // this thread's (level row, vector) slots of the box and their offsets
+    // from the box's first element; per plane only the first element moves
+    const int zs = ns * pad_row(nt);
+    int srow[kStageRegs], sq4[kStageRegs], soff[kStageRegs];
+#pragma unroll
+    for (int k = 0; k < kStageRegs; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      srow[k] = e / kStageF4;
+      sq4[k] = e % kStageF4;
+      soff[k] = srow[k] * zs + 4 * sq4[k];
+    }
+    auto stage_load = [&](const StageBox& b, int p) {
+      const T* __restrict__ first = base + pad_index(ns, nt, b.zl, p, b.tl4);
+#pragma unroll
+      for (int k = 0; k < kStageRegs; ++k)
+        reg[k] = (srow[k] < b.nzr && sq4[k] < b.nf4) ? ld4(first + soff[k])
+                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+      for (int k = 0; k < kStageRegs; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < kStageRows * kStageF4) tile[buf][e] = reg[k];
+      }
+    };
+    StageBox bcur = get_box(LO);
+    stage_load(bcur, LO);
+    stage_store(0);
+    __syncthreads();
+    for (int p = LO; p <= HI; ++p) {
+      const int cur = (p - LO) & 1;
+      StageBox bnext;
+      if (p < HI) {
+        bnext = get_box(p + 1);
+        stage_load(bnext, p + 1);
+      }
+      if (p >= lo && p <= hi)
+        sample_rows_lds<RPT, NL>(reinterpret_cast<const float*>(tile[cur]), bcur, ci, p, vz, zc,
+                                 nt, nz, acc0);
+      if (p < HI) stage_store(cur ^ 1);
+      __syncthreads();
+      bcur = bnext;
+    }
+  } else if (active) {
+    const int ntp = pad_row(nt), zs = ns * ntp;
+    const T* __restrict__ vb = base + pad_index(ns, nt, 0, 0, 0);
+    int p = lo;
+    for (; p < hi; p += 2) {
+      sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+      sample_rows<T, RPT, NL>(vb, ci, p + 1, vz, zc, nt, nz, ns, ntp, zs, acc1);
+    }
+    if (p == hi) sample_rows<T, RPT, NL>(vb, ci, p, vz, zc, nt, nz, ns, ntp, zs, acc0);
+  }
+  double part = 0.0;
+  if (active) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int r = r0 + j;
@@ -225,8 +511,12 @@ static void launch_project_rows(const GeomDev& g, const ViewInfo* views, const C
   dim3 block(256);
   dim3 grid((g.nu + 63) / 64, (g.nv + 4 * RPT - 1) / (4 * RPT), g.n_views);
   if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
-  hipLaunchKernelGGL((k_project<T, MODE, RPT, NL>), grid, block, 0, s, g, views, cols, padN, padT,
-                     gin, out, rl, partials);
+  if (RPT > 1)
+    hipLaunchKernelGGL((k_project_staged<T, MODE, (RPT > 1 ? RPT : 2), NL>), grid, block, 0, s, g,
+                       views, cols, padN, padT, gin, out, rl, partials);
+  else
+    hipLaunchKernelGGL((k_project<T, MODE, RPT, NL>), grid, block, 0, s, g, views, cols, padN, padT,
+                       gin, out, rl, partials);
 }
 
 template <typename T, int MODE>

@@ -32,28 +32,31 @@ inline size_t dtype_size(tfcb_dtype dt) { return dt == TFCB_F32 ? 4 : 2; }
 
 // ------------------------------------------------------- padded copies
 // The projector reads a volume through zero-padded copies laid out
-// [nz + 2 kZPad][ns][nt + 1] (kZPad zero slices below and above in z, one
-// zero column after every trans row) behind one leading zero element.
+// [nz + 2 kZPad][ns][pad_row(nt)] (kZPad zero slices below and above in z,
+// zero columns after every trans row up to a multiple of 4 elements) behind
+// 4 leading zero elements, so every row starts on a 4-element boundary.
 // Element (k, p, i) with k in [-kZPad, nz + kZPad), p in [0, ns), i in
-// [-1, nt] sits at 1 + ((k + kZPad) ns + p)(nt + 1) + i.  A thread that
-// samples several detector rows of one column loads a stack of up to
-// kZPad + 1 consecutive slices per plane; the pads make every such stack of a
-// plane where any of its rows is inside the volume lie inside the buffer, and
-// the taps that fall off the grid read exact zeros: no compares in the loop.
-// "native" copy: ns = ny, nt = nx (y-stepping views); "transposed" copy:
-// ns = nx, nt = ny (x-stepping views).  Only the interior is ever written;
-// the pads are cleared once per call.
+// [-4, pad_row(nt) - 1] sits at 4 + ((k + kZPad) ns + p) pad_row(nt) + i.
+// A thread that samples several detector rows of one column loads a stack
+// of up to kZPad + 1 consecutive slices per plane; the pads make every such
+// stack of a plane where any of its rows is inside the volume lie inside the
+// buffer, and the taps that fall off the grid read exact zeros: no compares
+// in the loop.  "native" copy: ns = ny, nt = nx (y-stepping views);
+// "transposed" copy: ns = nx, nt = ny (x-stepping views).  Only the interior
+// is ever written; the pads are cleared once per call.
 constexpr int kZPad = 5;
+constexpr int kPadLead = 4;
+__host__ __device__ __forceinline__ int pad_row(int nt) { return (nt + 1 + 3) & ~3; }
 inline size_t pad_elems(int ns, int nt, int nz) {
-  return 1 + (size_t)(nz + 2 * kZPad) * (size_t)ns * (size_t)(nt + 1);
+  return kPadLead + (size_t)(nz + 2 * kZPad) * (size_t)ns * (size_t)pad_row(nt);
 }
 inline size_t pad_elems_vol(int nx, int ny, int nz) {
-  // the larger of the two copies' sizes (they differ only in nt + 1)
+  // the larger of the two copies' sizes
   const size_t a = pad_elems(ny, nx, nz), b = pad_elems(nx, ny, nz);
   return a > b ? a : b;
 }
 __host__ __device__ __forceinline__ int pad_index(int ns, int nt, int k, int p, int i) {
-  return 1 + ((k + kZPad) * ns + p) * (nt + 1) + i;
+  return kPadLead + ((k + kZPad) * ns + p) * pad_row(nt) + i;
 }
 
 // ------------------------------------------------------------- geometry
