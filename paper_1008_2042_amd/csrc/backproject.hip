@@ -16,10 +16,11 @@
 // Mapping: 256-thread blocks of 64 (x) x 4 (y) voxel columns; each thread
 // accumulates a run of K voxels along z.  Per view the block first stages
 // its whole detector footprint (the bounding box of the projection of its
-// voxel box grown by one voxel, the support of the hat weights) into LDS
-// with coalesced row loads, stored column by column so that a column's rows
-// are adjacent, and every tap is an LDS read; a view whose footprint does
-// not fit the tile is read from global memory instead.
+// voxel box grown by one voxel, the support of the hat weights) into LDS as
+// running sums down each detector column (coalesced row loads), so that a z
+// segment's two sums are two differences of staged values and no row is
+// visited per voxel; a view whose footprint does not fit is read from global
+// memory row by row instead.
 // Within a column the footprint rows are split into z segments (rows whose
 // z index lies between two voxel centres): each row is read once, and the
 // segment sums of g and fr * g give both tent weights.
@@ -27,8 +28,9 @@
 
 namespace tfcb {
 
-constexpr int kZRun = 8;     // voxels per thread along z
-constexpr int kTile = 6144;  // LDS floats for one view's staged footprint (24 KB)
+constexpr int kZRun = 8;        // voxels per thread along z
+constexpr int kPrefTile = 5120; // LDS float pairs for one view's staged footprint (40 KB)
+constexpr int kQuarterRows = 16; // footprint rows per wave in the four-wave scan
 
 // One detector column's contribution to the K voxels of a z-run, with trans
 // weight wt.  Segment m = 0..K holds the rows whose z index
@@ -82,6 +84,37 @@ __device__ __forceinline__ void column_to_run(const P* __restrict__ col, int str
   }
 }
 
+// The same contribution from the column's prefix sums, staged in LDS:
+// pre[i] = (sum of g over rows r0 .. r0 + i - 1, sum of (r - rm) g over the
+// same rows) for i = 0..H, rm the footprint's middle row.  A segment [b, e)
+// has S = sum g = pre[e].x - pre[b].x, and with the z index of row r written
+// as zh_rm + zstep (r - rm) (zh_rm the projector's expression for row rm),
+// sum fr g = zstep (pre[e].y - pre[b].y) + (zh_rm - base) S, base the
+// segment's lower voxel; so no row is visited.
+template <int K>
+__device__ __forceinline__ void column_to_run_prefix(const float2* __restrict__ pre, int r0,
+                                                     int r1, int rb, int k0, float zh_rm,
+                                                     float zstep, float inv_s, float zc,
+                                                     float rc, float wt, float (&acc)[K]) {
+  float base = (float)(k0 - 1);  // z index of segment m's lower voxel
+  float coef = zh_rm - base;     // zh_rm - base, one less per segment
+  int b = rb;
+  float2 pb = pre[b - r0];
+#pragma unroll
+  for (int m = 0; m <= K; ++m) {
+    const int e = min(r1 + 1, max(b, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
+    const float2 pe = pre[e - r0];
+    const float S = pe.x - pb.x;
+    const float s1 = fmaf(zstep, pe.y - pb.y, coef * S);  // sum fr g
+    if (m > 0) acc[m - 1] = fmaf(wt, S - s1, acc[m - 1]);
+    if (m < K) acc[m] = fmaf(wt, s1, acc[m]);
+    b = e;
+    pb = pe;
+    base += 1.f;
+    coef -= 1.f;
+  }
+}
+
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
                                                      const ColInfo* __restrict__ cols,
@@ -89,7 +122,8 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
                                                      T* __restrict__ vol,
                                                      double* __restrict__ partials) {
   __shared__ double red[4];
-  __shared__ float tile[kTile];
+  __shared__ float2 pre[kPrefTile];
+  __shared__ float2 qtot[3][128];  // quarter totals of the four-wave scan
   __shared__ float cbox[2][8];  // projected corner columns / rows
   extern __shared__ float vz_tab[];  // vz_r = (r - (nv-1)/2) dv/dz, as the projector forms it
   const float rc = 0.5f * (float)(g.nv - 1);
@@ -144,37 +178,14 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
     const int c0 = max(0, (int)floorf(umin) - 1), c1 = min(g.nu - 1, (int)ceilf(umax) + 1);
     const int r0 = max(0, (int)floorf(vmin) - 1), r1 = min(g.nv - 1, (int)ceilf(vmax) + 1);
     const int W = c1 - c0 + 1, H = r1 - r0 + 1;
-    // column-major tile, odd column stride: a column's rows are adjacent
-    // (two per LDS read) and adjacent columns fall in different banks
-    const int Hs = H | 1;
-    const bool staged = W > 0 && H > 0 && W * Hs <= kTile;
-    if (staged) {
-      // each wave takes rows wave, wave + 4, ...; a lane loads 4 rows x 2
-      // columns before it writes any, so 8 loads per lane are in flight
-      for (int cb = 0; cb < W; cb += 128) {
-        for (int rr = wave; rr < H; rr += 16) {
-          float v[4][2];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int row = rr + 4 * u, cc = cb + lane + 64 * h;
-              v[u][h] = (row < H && cc < W) ? ld(rview + (size_t)(r0 + row) * g.nu + (c0 + cc))
-                                            : 0.f;
-            }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int row = rr + 4 * u, cc = cb + lane + 64 * h;
-              if (row < H && cc < W) tile[cc * Hs + row] = v[u][h];
-            }
-        }
-      }
-    }
-    __syncthreads();
-    if (!active || W <= 0 || H <= 0) continue;
-
+    const int rm = r0 + (H >> 1);
+    // column-major prefix sums, H + 1 pairs per column, odd column stride so
+    // that adjacent columns fall in different banks
+    const int Hp = (H + 1) | 1;
+    const bool staged = W > 0 && H > 0 && W * Hp <= kPrefTile;
+    // This thread's plane, trans index and bracket of columns, and their
+    // table records, loaded before the staging so that their latency
+    // overlaps it.
     int p, t;
     float Xa, Ya, Xb, Yb;  // the trans neighbours t - 1 and t + 1 on plane p
     if (vi.step_x) {
@@ -202,18 +213,105 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
     // a column has a non-zero trans weight only strictly between ca and cb
     // (the margin covers the reciprocal's error); all of them lie inside
     // the footprint box
-    const int clo = max(c0, (int)floorf(fminf(ca, cb) - 1e-3f) + 1);
-    const int chi = min(c1, (int)ceilf(fmaxf(ca, cb) + 1e-3f) - 1);
+    const int clo = !active ? 1 : max(c0, (int)floorf(fminf(ca, cb) - 1e-3f) + 1);
+    const int chi = !active ? 0 : min(c1, (int)ceilf(fmaxf(ca, cb) + 1e-3f) - 1);
     const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
+    float4 pf0[3];
+    int4 pf1[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int c = min(clo + q, g.nu - 1);
+      if (clo + q <= chi) {
+        pf0[q] = reinterpret_cast<const float4*>(cview + c)[0];
+        pf1[q] = reinterpret_cast<const int4*>(cview + c)[1];
+      }
+    }
+    if (staged && W <= 2 * 64 && H <= 4 * kQuarterRows) {
+      // Wave w scans rows [w HQ, (w + 1) HQ) of both 64-column chunks: the
+      // loads of both are issued together (one memory latency), the running
+      // sums start from zero at the quarter's first row, and the quarter's
+      // totals go to LDS; after a barrier each quarter adds the totals of
+      // the quarters above it (the second sum is over absolute row offsets
+      // r - rm, so the parts simply add).
+      const int HQ = (H + 3) >> 2;
+      const int q0 = wave * HQ, q1 = min(H, q0 + HQ);
+      float v[2][kQuarterRows];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cc = lane + 64 * h;
+        const T* __restrict__ src = rview + (size_t)r0 * g.nu + (c0 + min(cc, W - 1));
+#pragma unroll
+        for (int u = 0; u < kQuarterRows; ++u)
+          v[h][u] = (q0 + u < q1 && cc < W) ? ld(src + (size_t)(q0 + u) * g.nu) : 0.f;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cc = lane + 64 * h;
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int u = 0; u < kQuarterRows; ++u) {
+          if (q0 + u < q1 && cc < W) {
+            s0 += v[h][u];
+            s1 = fmaf((float)(r0 + q0 + u - rm), v[h][u], s1);
+            pre[cc * Hp + q0 + u + 1] = make_float2(s0, s1);
+          }
+        }
+        if (cc < W && wave < 3) qtot[wave][cc] = make_float2(s0, s1);
+        if (cc < W && wave == 0) pre[cc * Hp] = make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+      if (wave > 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int cc = lane + 64 * h;
+          if (cc < W) {
+            float2 carry = qtot[0][cc];
+            for (int w = 1; w < wave; ++w) {
+              carry.x += qtot[w][cc].x;
+              carry.y += qtot[w][cc].y;
+            }
+            for (int r = q0; r < q1; ++r) {
+              float2 e = pre[cc * Hp + r + 1];
+              e.x += carry.x;
+              e.y += carry.y;
+              pre[cc * Hp + r + 1] = e;
+            }
+          }
+        }
+      }
+    } else if (staged) {
+      // a wave scans 64 columns down the footprint's rows with coalesced
+      // loads, 8 rows in flight per lane
+      for (int chunk = wave * 64; chunk < W; chunk += 256) {
+        const int cc = chunk + lane;
+        const bool own = cc < W;
+        const T* __restrict__ src = rview + (size_t)r0 * g.nu + (c0 + min(cc, W - 1));
+        float2* __restrict__ dst = pre + cc * Hp;
+        float s0 = 0.f, s1 = 0.f;
+        if (own) dst[0] = make_float2(0.f, 0.f);
+        for (int rr = 0; rr < H; rr += 8) {
+          float w8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) w8[u] = rr + u < H ? ld(src + (size_t)(rr + u) * g.nu) : 0.f;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (rr + u < H) {
+              s0 += w8[u];
+              s1 = fmaf((float)(r0 + rr + u - rm), w8[u], s1);
+              if (own) dst[rr + u + 1] = make_float2(s0, s1);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (!active || W <= 0 || H <= 0) continue;
     const float fp = (float)p;
-    for (int c = clo; c <= chi; ++c) {
-      // both halves of the 32-byte record in two vector loads, issued together
-      const float4 h0 = reinterpret_cast<const float4*>(cview + c)[0];
-      const int4 h1 = reinterpret_cast<const int4*>(cview + c)[1];
-      if (p < h1.z || p > h1.w) continue;  // plane outside 0 < tau < 1
+    auto column = [&](int c, const float4& h0, const int4& h1) {
       const float th = fmaf(fp, h0.y, h0.x);
       const float wt = 1.f - fabsf(th - (float)t);
-      if (wt <= 0.f) continue;
+      // plane outside 0 < tau < 1, or no trans weight
+      if (p < h1.z || p > h1.w || !(wt > 0.f)) return;
       const float tau = fmaf(fp, h0.w, h0.z);
       // Segment m = the rows of z index in [k0 - 1 + m, k0 + m): they give
       // (1 - fr) of their value to voxel k0 - 1 + m and fr to voxel k0 + m.
@@ -221,12 +319,18 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
       const float inv_s = __builtin_amdgcn_rcpf(zstep);
       const int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
       if (staged)
-        column_to_run<K>(tile + (c - c0) * Hs, 1, r0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt,
-                         vz_tab, g.nv, acc);
+        column_to_run_prefix<K>(pre + (c - c0) * Hp, r0, r1, rb, k0, fmaf(tau, vz_tab[rm], zc),
+                                zstep, inv_s, zc, rc, wt, acc);
       else
         column_to_run<K>(rview + c, g.nu, 0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
                          g.nv, acc);
-    }
+    };
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (clo + q <= chi) column(clo + q, pf0[q], pf1[q]);
+    for (int c = clo + 3; c <= chi; ++c)
+      column(c, reinterpret_cast<const float4*>(cview + c)[0],
+             reinterpret_cast<const int4*>(cview + c)[1]);
   }
 
   double part = 0.0;
