@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
   __shared__ double red[4];
   __shared__ float2 pre[kPrefTile];
   __shared__ float2 qtot[3][128];  // quarter totals of the four-wave scan
-  __shared__ float cbox[2][8];  // projected corner columns / rows
+  __shared__ float cbox[2][2][8];  // projected corner columns / rows, two views
   extern __shared__ float vz_tab[];  // vz_r = (r - (nv-1)/2) dv/dz, as the projector forms it
   const float rc = 0.5f * (float)(g.nv - 1);
   for (int r = threadIdx.x; r < g.nv; r += blockDim.x) vz_tab[r] = ((float)r - rc) * g.dvdz;
@@ -153,38 +153,71 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.f;
 
-  for (int view = 0; view < g.n_views; ++view) {
-    const ViewInfo vi = views[view];
-    const T* __restrict__ rview = rl + (size_t)view * g.nv * g.nu;
-    // ---- footprint box: project the 8 corners of the grown voxel box
-    __syncthreads();  // previous view's tile reads are done
+  // footprint box of a view: the 8 corners of the grown voxel box
+  // projected to (column, row), one corner per thread
+  auto corners = [&](int view, int buf) {
     if (threadIdx.x < 8) {
+      const ViewInfo vc = views[view];
       const float cx = (threadIdx.x & 1) ? bx1 : bx0;
       const float cy = (threadIdx.x & 2) ? by1 : by0;
       const float cz = (threadIdx.x & 4) ? bz1 : bz0;
-      const float den = __builtin_amdgcn_rcpf(g.sad - (cx * vi.cs + cy * vi.sn));
-      cbox[0][threadIdx.x] = fmaf(g.sdd * (-cx * vi.sn + cy * vi.cs) * den, inv_du, cu);
-      cbox[1][threadIdx.x] = fmaf(g.sdd * cz * den, inv_dv, rc);
+      const float den = __builtin_amdgcn_rcpf(g.sad - (cx * vc.cs + cy * vc.sn));
+      cbox[buf][0][threadIdx.x] = fmaf(g.sdd * (-cx * vc.sn + cy * vc.cs) * den, inv_du, cu);
+      cbox[buf][1][threadIdx.x] = fmaf(g.sdd * cz * den, inv_dv, rc);
     }
-    __syncthreads();
-    float umin = cbox[0][0], umax = umin, vmin = cbox[1][0], vmax = vmin;
+  };
+  corners(0, 0);
+  __syncthreads();
+  // wave index as a scalar, so that the scan's row bounds are uniform branches
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+
+  // Per view, two barriers: B1 (the previous view's reads of the tile are
+  // done, the quarter totals are visible) and B2 (the tile is complete).
+  // The next view's corners are projected between them into the other
+  // half of cbox.
+  for (int view = 0; view < g.n_views; ++view) {
+    const ViewInfo vi = views[view];
+    const T* __restrict__ rview = rl + (size_t)view * g.nv * g.nu;
+    const int cb = view & 1;
+    float umin = cbox[cb][0][0], umax = umin, vmin = cbox[cb][1][0], vmax = vmin;
 #pragma unroll
     for (int e = 1; e < 8; ++e) {
-      umin = fminf(umin, cbox[0][e]);
-      umax = fmaxf(umax, cbox[0][e]);
-      vmin = fminf(vmin, cbox[1][e]);
-      vmax = fmaxf(vmax, cbox[1][e]);
+      umin = fminf(umin, cbox[cb][0][e]);
+      umax = fmaxf(umax, cbox[cb][0][e]);
+      vmin = fminf(vmin, cbox[cb][1][e]);
+      vmax = fmaxf(vmax, cbox[cb][1][e]);
     }
-    const int c0 = max(0, (int)floorf(umin) - 1), c1 = min(g.nu - 1, (int)ceilf(umax) + 1);
-    const int r0 = max(0, (int)floorf(vmin) - 1), r1 = min(g.nv - 1, (int)ceilf(vmax) + 1);
+    // the same in every lane: held as scalars
+    const int c0 = __builtin_amdgcn_readfirstlane(max(0, (int)floorf(umin) - 1));
+    const int c1 = __builtin_amdgcn_readfirstlane(min(g.nu - 1, (int)ceilf(umax) + 1));
+    const int r0 = __builtin_amdgcn_readfirstlane(max(0, (int)floorf(vmin) - 1));
+    const int r1 = __builtin_amdgcn_readfirstlane(min(g.nv - 1, (int)ceilf(vmax) + 1));
     const int W = c1 - c0 + 1, H = r1 - r0 + 1;
     const int rm = r0 + (H >> 1);
     // column-major prefix sums, H + 1 pairs per column, odd column stride so
     // that adjacent columns fall in different banks
     const int Hp = (H + 1) | 1;
     const bool staged = W > 0 && H > 0 && W * Hp <= kPrefTile;
+    const bool quarters = staged && W <= 2 * 64 && H <= 4 * kQuarterRows;
+    // Four-wave scan of footprints up to 128 x 64: wave w takes rows
+    // [w HQ, (w + 1) HQ) of both 64-column chunks.  Before B1 it loads them
+    // (the loads of both chunks in flight together) and publishes the
+    // quarter's totals; after B1 it writes the running sums with the totals
+    // of the quarters above added (the second sum is over absolute row
+    // offsets r - rm, so the parts simply add).
+    const int HQ = (H + 3) >> 2;
+    const int q0 = wv * HQ, nq = quarters ? max(0, min(H - q0, HQ)) : 0;
+    float qv[2][kQuarterRows];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cc = min(lane + 64 * h, max(W, 1) - 1);
+      const T* __restrict__ src = rview + (size_t)(r0 + q0) * g.nu + (c0 + cc);
+#pragma unroll
+      for (int u = 0; u < kQuarterRows; ++u)
+        qv[h][u] = (u < nq && (h == 0 || W > 64)) ? ld(src + (size_t)u * g.nu) : 0.f;
+    }
     // This thread's plane, trans index and bracket of columns, and their
-    // table records, loaded before the staging so that their latency
+    // table records, loaded before the tile is built so that their latency
     // overlaps it.
     int p, t;
     float Xa, Ya, Xb, Yb;  // the trans neighbours t - 1 and t + 1 on plane p
@@ -209,12 +242,12 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
                      __builtin_amdgcn_rcpf(g.sad - (Xa * vi.cs + Ya * vi.sn));
     const float ub = g.sdd * (-Xb * vi.sn + Yb * vi.cs) *
                      __builtin_amdgcn_rcpf(g.sad - (Xb * vi.cs + Yb * vi.sn));
-    const float ca = fmaf(ua, inv_du, cu), cb = fmaf(ub, inv_du, cu);
-    // a column has a non-zero trans weight only strictly between ca and cb
+    const float ca = fmaf(ua, inv_du, cu), cbc = fmaf(ub, inv_du, cu);
+    // a column has a non-zero trans weight only strictly between ca and cbc
     // (the margin covers the reciprocal's error); all of them lie inside
     // the footprint box
-    const int clo = !active ? 1 : max(c0, (int)floorf(fminf(ca, cb) - 1e-3f) + 1);
-    const int chi = !active ? 0 : min(c1, (int)ceilf(fmaxf(ca, cb) + 1e-3f) - 1);
+    const int clo = !active ? 1 : max(c0, (int)floorf(fminf(ca, cbc) - 1e-3f) + 1);
+    const int chi = !active ? 0 : min(c1, (int)ceilf(fmaxf(ca, cbc) + 1e-3f) - 1);
     const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
     float4 pf0[3];
     int4 pf1[3];
@@ -226,55 +259,40 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
         pf1[q] = reinterpret_cast<const int4*>(cview + c)[1];
       }
     }
-    if (staged && W <= 2 * 64 && H <= 4 * kQuarterRows) {
-      // Wave w scans rows [w HQ, (w + 1) HQ) of both 64-column chunks: the
-      // loads of both are issued together (one memory latency), the running
-      // sums start from zero at the quarter's first row, and the quarter's
-      // totals go to LDS; after a barrier each quarter adds the totals of
-      // the quarters above it (the second sum is over absolute row offsets
-      // r - rm, so the parts simply add).
-      const int HQ = (H + 3) >> 2;
-      const int q0 = wave * HQ, q1 = min(H, q0 + HQ);
-      float v[2][kQuarterRows];
+    if (quarters && wv < 3) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int cc = lane + 64 * h;
-        const T* __restrict__ src = rview + (size_t)r0 * g.nu + (c0 + min(cc, W - 1));
-#pragma unroll
-        for (int u = 0; u < kQuarterRows; ++u)
-          v[h][u] = (q0 + u < q1 && cc < W) ? ld(src + (size_t)(q0 + u) * g.nu) : 0.f;
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int cc = lane + 64 * h;
         float s0 = 0.f, s1 = 0.f;
 #pragma unroll
         for (int u = 0; u < kQuarterRows; ++u) {
-          if (q0 + u < q1 && cc < W) {
-            s0 += v[h][u];
-            s1 = fmaf((float)(r0 + q0 + u - rm), v[h][u], s1);
-            pre[cc * Hp + q0 + u + 1] = make_float2(s0, s1);
-          }
+          s0 += qv[h][u];
+          s1 = fmaf((float)(r0 + q0 + u - rm), qv[h][u], s1);
         }
-        if (cc < W && wave < 3) qtot[wave][cc] = make_float2(s0, s1);
-        if (cc < W && wave == 0) pre[cc * Hp] = make_float2(0.f, 0.f);
+        const int cc = lane + 64 * h;
+        if (cc < W) qtot[wv][cc] = make_float2(s0, s1);
       }
-      __syncthreads();
-      if (wave > 0) {
+    }
+    __syncthreads();  // B1
+    if (view + 1 < g.n_views) corners(view + 1, cb ^ 1);
+    if (quarters) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int cc = lane + 64 * h;
-          if (cc < W) {
-            float2 carry = qtot[0][cc];
-            for (int w = 1; w < wave; ++w) {
-              carry.x += qtot[w][cc].x;
-              carry.y += qtot[w][cc].y;
-            }
-            for (int r = q0; r < q1; ++r) {
-              float2 e = pre[cc * Hp + r + 1];
-              e.x += carry.x;
-              e.y += carry.y;
-              pre[cc * Hp + r + 1] = e;
+      for (int h = 0; h < 2; ++h) {
+        const int cc = lane + 64 * h;
+        if (cc < W) {
+          float s0 = 0.f, s1 = 0.f;
+          for (int w = 0; w < wv; ++w) {
+            const float2 qt = qtot[w][cc];
+            s0 += qt.x;
+            s1 += qt.y;
+          }
+          float2* __restrict__ dst = pre + cc * Hp + q0 + 1;
+          if (wv == 0) dst[-1] = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int u = 0; u < kQuarterRows; ++u) {
+            if (u < nq) {
+              s0 += qv[h][u];
+              s1 = fmaf((float)(r0 + q0 + u - rm), qv[h][u], s1);
+              dst[u] = make_float2(s0, s1);
             }
           }
         }
@@ -304,7 +322,7 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
         }
       }
     }
-    __syncthreads();
+    __syncthreads();  // B2
     if (!active || W <= 0 || H <= 0) continue;
     const float fp = (float)p;
     auto column = [&](int c, const float4& h0, const int4& h1) {
