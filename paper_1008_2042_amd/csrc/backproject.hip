@@ -116,7 +116,7 @@ __device__ __forceinline__ void column_to_run_prefix(const float2* __restrict__ 
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
+__global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
                                                      const ColInfo* __restrict__ cols,
                                                      const T* __restrict__ rl,
                                                      T* __restrict__ vol,
@@ -194,27 +194,40 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
     const int r1 = __builtin_amdgcn_readfirstlane(min(g.nv - 1, (int)ceilf(vmax) + 1));
     const int W = c1 - c0 + 1, H = r1 - r0 + 1;
     const int rm = r0 + (H >> 1);
-    // column-major prefix sums, H + 1 pairs per column, odd column stride so
-    // that adjacent columns fall in different banks
-    const int Hp = (H + 1) | 1;
-    const bool staged = W > 0 && H > 0 && W * Hp <= kPrefTile;
-    const bool quarters = staged && W <= 2 * 64 && H <= 4 * kQuarterRows;
-    // Four-wave scan of footprints up to 128 x 64: wave w takes rows
-    // [w HQ, (w + 1) HQ) of both 64-column chunks.  Before B1 it loads them
-    // (the loads of both chunks in flight together) and publishes the
-    // quarter's totals; after B1 it writes the running sums with the totals
-    // of the quarters above added (the second sum is over absolute row
-    // offsets r - rm, so the parts simply add).
-    const int HQ = (H + 3) >> 2;
-    const int q0 = wv * HQ, nq = quarters ? max(0, min(H - q0, HQ)) : 0;
+    // Column-major prefix sums with an odd column stride Hp (adjacent columns
+    // in different banks).  Four-wave scan of footprints up to 128 x 64:
+    // wave w takes footprint rows [16 w, 16 w + 16) of both 64-column
+    // chunks, and Hp = 16 ceil(H / 16) + 1 leaves room for the last
+    // quarter's rows past H, so every quarter loads and writes 16 rows
+    // without per-row conditions (rows past H load row r1 again and land in
+    // the column's padding, which is never read; no later quarter uses that
+    // wave's totals).  Other footprints: stride (H + 1) | 1, scanned a
+    // column per lane.
+    const int Hq = 16 * ((H + 15) >> 4) + 1;
+    const bool quarters = W > 0 && H > 0 && W <= 2 * 64 && H <= 4 * kQuarterRows &&
+                          W * Hq <= kPrefTile;
+    const int Hp = quarters ? Hq : ((H + 1) | 1);
+    const bool staged = quarters || (W > 0 && H > 0 && W * Hp <= kPrefTile);
+    const int q0 = kQuarterRows * wv;
+    const bool qrows = quarters && q0 < H;  // this wave has rows to scan
+    const float wq = (float)(r0 + q0 - rm);  // row offset of the quarter's first row
     float qv[2][kQuarterRows];
+    if (qrows) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int cc = min(lane + 64 * h, max(W, 1) - 1);
-      const T* __restrict__ src = rview + (size_t)(r0 + q0) * g.nu + (c0 + cc);
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && W <= 64) break;
+        // a scalar row pointer stepped down the rows, a 32-bit column offset per lane
+        const uint32_t cb = (uint32_t)(min(lane + 64 * h, W - 1) * sizeof(T));
+        const T* __restrict__ rp = rview + (size_t)(r0 + q0) * g.nu + c0;
+        int row = r0 + q0;
 #pragma unroll
-      for (int u = 0; u < kQuarterRows; ++u)
-        qv[h][u] = (u < nq && (h == 0 || W > 64)) ? ld(src + (size_t)u * g.nu) : 0.f;
+        for (int u = 0; u < kQuarterRows; ++u) {
+          qv[h][u] = ld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(rp) + cb));
+          const bool step = row < r1;
+          rp += step ? g.nu : 0;
+          row += step ? 1 : 0;
+        }
+      }
     }
     // This thread's plane, trans index and bracket of columns, and their
     // table records, loaded before the tile is built so that their latency
@@ -259,14 +272,16 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
         pf1[q] = reinterpret_cast<const int4*>(cview + c)[1];
       }
     }
-    if (quarters && wv < 3) {
+    if (qrows && wv < 3) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        float s0 = 0.f, s1 = 0.f;
+        if (h == 1 && W <= 64) break;
+        float s0 = 0.f, s1 = 0.f, w = wq;
 #pragma unroll
         for (int u = 0; u < kQuarterRows; ++u) {
           s0 += qv[h][u];
-          s1 = fmaf((float)(r0 + q0 + u - rm), qv[h][u], s1);
+          s1 = fmaf(w, qv[h][u], s1);
+          w += 1.f;
         }
         const int cc = lane + 64 * h;
         if (cc < W) qtot[wv][cc] = make_float2(s0, s1);
@@ -274,14 +289,15 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
     }
     __syncthreads();  // B1
     if (view + 1 < g.n_views) corners(view + 1, cb ^ 1);
-    if (quarters) {
+    if (qrows) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
+        if (h == 1 && W <= 64) break;
         const int cc = lane + 64 * h;
         if (cc < W) {
-          float s0 = 0.f, s1 = 0.f;
-          for (int w = 0; w < wv; ++w) {
-            const float2 qt = qtot[w][cc];
+          float s0 = 0.f, s1 = 0.f, w = wq;
+          for (int k = 0; k < wv; ++k) {
+            const float2 qt = qtot[k][cc];
             s0 += qt.x;
             s1 += qt.y;
           }
@@ -289,11 +305,10 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev g, const ViewInfo* 
           if (wv == 0) dst[-1] = make_float2(0.f, 0.f);
 #pragma unroll
           for (int u = 0; u < kQuarterRows; ++u) {
-            if (u < nq) {
-              s0 += qv[h][u];
-              s1 = fmaf((float)(r0 + q0 + u - rm), qv[h][u], s1);
-              dst[u] = make_float2(s0, s1);
-            }
+            s0 += qv[h][u];
+            s1 = fmaf(w, qv[h][u], s1);
+            w += 1.f;
+            dst[u] = make_float2(s0, s1);
           }
         }
       }
