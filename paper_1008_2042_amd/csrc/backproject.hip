@@ -84,34 +84,56 @@ __device__ __forceinline__ void column_to_run(const P* __restrict__ col, int str
   }
 }
 
+// -ceil(a) as floor(-a), in one conversion
+__device__ __forceinline__ int neg_ceil(float a) {
+  int r;
+  asm("v_cvt_flr_i32_f32_e64 %0, -%1" : "=v"(r) : "v"(a));
+  return r;
+}
+// x clamped to [lo, hi]
+__device__ __forceinline__ int clamp3(int x, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
+// b - 8 f for |f| < 2^23
+__device__ __forceinline__ int minus8_add(int f, int b) {
+  int r;
+  asm("v_mad_i32_i24 %0, %1, -8, %2" : "=v"(r) : "v"(f), "v"(b));
+  return r;
+}
+
 // The same contribution from the column's prefix sums, staged in LDS:
-// pre[i] = (sum of g over rows r0 .. r0 + i - 1, sum of (r - rm) g over the
-// same rows) for i = 0..H, rm the footprint's middle row.  A segment [b, e)
-// has S = sum g = pre[e].x - pre[b].x, and with the z index of row r written
-// as zh_rm + zstep (r - rm) (zh_rm the projector's expression for row rm),
-// sum fr g = zstep (pre[e].y - pre[b].y) + (zh_rm - base) S, base the
-// segment's lower voxel; so no row is visited.
+// entry e of the column (byte offset colb + 8 e, e = r0..r1 + 1) holds
+// (sum of g over rows r0 .. e - 1, sum of (r - rm) g over the same rows),
+// rm the footprint's middle row.  A segment [b, e) has S = sum g = the
+// difference of the two entries' first parts, and with the z index of row r
+// written as zh_rm + zstep (r - rm) (zh_rm the projector's expression for
+// row rm), sum fr g = zstep (difference of the second parts) +
+// (zh_rm - base) S, base the segment's lower voxel; so no row is visited.
+// Segment bounds: the first row of z index >= k0 - 1 + m is
+// ceil((k0 - 1 + m - zc) / zstep + rc), clamped to [r0, r1 + 1] (a row
+// misplaced by rounding at a bound has fr within an ulp of 0 or 1); the
+// argument a grows by inv_s = 1 / zstep per segment.  Bounds are handled as
+// f = -e so that the clamp and the address take one instruction each.
 template <int K>
-__device__ __forceinline__ void column_to_run_prefix(const float2* __restrict__ pre, int r0,
-                                                     int r1, int rb, int k0, float zh_rm,
-                                                     float zstep, float inv_s, float zc,
-                                                     float rc, float wt, float (&acc)[K]) {
-  float base = (float)(k0 - 1);  // z index of segment m's lower voxel
-  float coef = zh_rm - base;     // zh_rm - base, one less per segment
-  int b = rb;
-  float2 pb = pre[b - r0];
+__device__ __forceinline__ void column_to_run_prefix(const float2* __restrict__ pre, int colb,
+                                                     int nlo, int nhi, float a, float inv_s,
+                                                     float coef, float zstep, float wt,
+                                                     float (&acc)[K]) {
+  const char* __restrict__ base = reinterpret_cast<const char*>(pre);
+  float2 pb = *reinterpret_cast<const float2*>(base + minus8_add(clamp3(neg_ceil(a), nlo, nhi), colb));
 #pragma unroll
   for (int m = 0; m <= K; ++m) {
-    const int e = min(r1 + 1, max(b, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
-    const float2 pe = pre[e - r0];
+    a += inv_s;
+    const float2 pe =
+        *reinterpret_cast<const float2*>(base + minus8_add(clamp3(neg_ceil(a), nlo, nhi), colb));
     const float S = pe.x - pb.x;
     const float s1 = fmaf(zstep, pe.y - pb.y, coef * S);  // sum fr g
     if (m > 0) acc[m - 1] = fmaf(wt, S - s1, acc[m - 1]);
     if (m < K) acc[m] = fmaf(wt, s1, acc[m]);
-    b = e;
     pb = pe;
-    base += 1.f;
-    coef -= 1.f;
+    coef -= 1.f;  // coef = zh_rm - base
   }
 }
 
@@ -340,30 +362,46 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     __syncthreads();  // B2
     if (!active || W <= 0 || H <= 0) continue;
     const float fp = (float)p;
-    auto column = [&](int c, const float4& h0, const int4& h1) {
-      const float th = fmaf(fp, h0.y, h0.x);
-      const float wt = 1.f - fabsf(th - (float)t);
-      // plane outside 0 < tau < 1, or no trans weight
-      if (p < h1.z || p > h1.w || !(wt > 0.f)) return;
-      const float tau = fmaf(fp, h0.w, h0.z);
-      // Segment m = the rows of z index in [k0 - 1 + m, k0 + m): they give
-      // (1 - fr) of their value to voxel k0 - 1 + m and fr to voxel k0 + m.
-      const float zstep = tau * g.dvdz;
-      const float inv_s = __builtin_amdgcn_rcpf(zstep);
-      const int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
-      if (staged)
-        column_to_run_prefix<K>(pre + (c - c0) * Hp, r0, r1, rb, k0, fmaf(tau, vz_tab[rm], zc),
-                                zstep, inv_s, zc, rc, wt, acc);
-      else
+    if (staged) {
+      // Every column of the bracket is evaluated; one whose plane lies
+      // outside 0 < tau < 1 or with no trans weight gets weight 0 (its table
+      // entries are finite and its bounds are clamped into the tile).
+      const float kz = (float)(k0 - 1) - zc;
+      const float vzm = ((float)rm - rc) * g.dvdz;  // the projector's vz for row rm
+      const int nlo = -(r1 + 1), nhi = -r0;
+      auto column = [&](int c, const float4& h0, const int4& h1) {
+        const float th = fmaf(fp, h0.y, h0.x);
+        float wt = 1.f - fabsf(th - (float)t);
+        wt = (p >= h1.z && p <= h1.w && wt > 0.f) ? wt : 0.f;
+        const float tau = fmaf(fp, h0.w, h0.z);
+        const float zstep = tau * g.dvdz;
+        const float inv_s = __builtin_amdgcn_rcpf(zstep);
+        const int colb = ((c - c0) * Hp - r0) * (int)sizeof(float2);
+        column_to_run_prefix<K>(pre, colb, nlo, nhi, fmaf(kz, inv_s, rc), inv_s,
+                                fmaf(tau, vzm, zc) - (float)(k0 - 1), zstep, wt, acc);
+      };
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (clo + q <= chi) column(clo + q, pf0[q], pf1[q]);
+      for (int c = clo + 3; c <= chi; ++c)
+        column(c, reinterpret_cast<const float4*>(cview + c)[0],
+               reinterpret_cast<const int4*>(cview + c)[1]);
+    } else {
+      for (int c = clo; c <= chi; ++c) {
+        const float4 h0 = reinterpret_cast<const float4*>(cview + c)[0];
+        const int4 h1 = reinterpret_cast<const int4*>(cview + c)[1];
+        const float th = fmaf(fp, h0.y, h0.x);
+        const float wt = 1.f - fabsf(th - (float)t);
+        // plane outside 0 < tau < 1, or no trans weight
+        if (p < h1.z || p > h1.w || !(wt > 0.f)) continue;
+        const float tau = fmaf(fp, h0.w, h0.z);
+        const float zstep = tau * g.dvdz;
+        const float inv_s = __builtin_amdgcn_rcpf(zstep);
+        const int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
         column_to_run<K>(rview + c, g.nu, 0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
                          g.nv, acc);
-    };
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      if (clo + q <= chi) column(clo + q, pf0[q], pf1[q]);
-    for (int c = clo + 3; c <= chi; ++c)
-      column(c, reinterpret_cast<const float4*>(cview + c)[0],
-             reinterpret_cast<const int4*>(cview + c)[1]);
+      }
+    }
   }
 
   double part = 0.0;
