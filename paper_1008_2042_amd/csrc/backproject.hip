@@ -22,8 +22,8 @@
 // visited per voxel; a view whose footprint does not fit is read from global
 // memory row by row instead.
 // Within a column the footprint rows are split into z segments (rows whose
-// z index lies between two voxel centres): each row is read once, and the
-// segment sums of g and fr * g give both tent weights.
+// z index lies between two voxel centres); the segment sums of g and fr * g
+// give both tent weights.
 #include "tfcb_internal.h"
 
 namespace tfcb {
