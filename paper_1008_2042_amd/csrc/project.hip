@@ -219,12 +219,23 @@ constexpr int kStageRows = 24;  // level rows per staged plane
 constexpr int kStageRegs = (kStageRows * kStageF4 + 255) / 256;
 constexpr int kStageBoxes = 1024;  // planes whose boxes a block tabulates in LDS
 
-template <typename T> __device__ __forceinline__ float4 ld4(const T* p);
-template <> __device__ __forceinline__ float4 ld4<float>(const float* p) {
-  return *reinterpret_cast<const float4*>(p);
+// Four consecutive stored elements, loaded as they are stored (a float4, or
+// 8 bytes of FP16/BF16) and widened to FP32 only when written to LDS, so
+// that the loads of the next plane stay in flight while this plane is
+// sampled.
+template <typename T> struct Raw4 { using type = uint2; };
+template <> struct Raw4<float> { using type = float4; };
+template <typename T>
+__device__ __forceinline__ typename Raw4<T>::type ld_raw4(const T* p) {
+  return *reinterpret_cast<const typename Raw4<T>::type*>(p);
 }
-template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p) {
-  const uint2 u = *reinterpret_cast<const uint2*>(p);
+template <typename T>
+__device__ __forceinline__ typename Raw4<T>::type raw4_zero() {
+  return typename Raw4<T>::type{};
+}
+template <typename T> __device__ __forceinline__ float4 widen4(typename Raw4<T>::type u);
+template <> __device__ __forceinline__ float4 widen4<float>(float4 u) { return u; }
+template <> __device__ __forceinline__ float4 widen4<__half>(uint2 u) {
   __half_raw h0, h1, h2, h3;
   h0.x = (unsigned short)(u.x & 0xffffu);
   h1.x = (unsigned short)(u.x >> 16);
@@ -233,9 +244,8 @@ template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p) {
   return make_float4(__half2float(__half(h0)), __half2float(__half(h1)),
                      __half2float(__half(h2)), __half2float(__half(h3)));
 }
-template <> __device__ __forceinline__ float4 ld4<__hip_bfloat16>(const __hip_bfloat16* p) {
+template <> __device__ __forceinline__ float4 widen4<__hip_bfloat16>(uint2 u) {
   // a bfloat16 is the upper half of the float with the same bits
-  const uint2 u = *reinterpret_cast<const uint2*>(p);
   return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                      __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomDev g, const ViewInf
       }
       return b;
     };
-    float4 reg[kStageRegs];
+    typename Raw4<T>::type reg[kStageRegs];
     // this thread's (level row, vector) slots of the box and their offsets
     // from the box's first element; per plane only the first element moves
     const int zs = ns * pad_row(nt);
@@ -409,14 +419,13 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomDev g, const ViewInf
       const T* __restrict__ first = base + pad_index(ns, nt, b.zl, p, b.tl4);
 #pragma unroll
       for (int k = 0; k < kStageRegs; ++k)
-        reg[k] = (srow[k] < b.nzr && sq4[k] < b.nf4) ? ld4(first + soff[k])
-                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        reg[k] = (srow[k] < b.nzr && sq4[k] < b.nf4) ? ld_raw4(first + soff[k]) : raw4_zero<T>();
     };
     auto stage_store = [&](int buf) {
 #pragma unroll
       for (int k = 0; k < kStageRegs; ++k) {
         const int e = threadIdx.x + 256 * k;
-        if (e < kStageRows * kStageF4) tile[buf][e] = reg[k];
+        if (e < kStageRows * kStageF4) tile[buf][e] = widen4<T>(reg[k]);
       }
     };
     StageBox bcur = get_box(LO);
