@@ -33,54 +33,47 @@ constexpr int kPrefTile = 5120; // LDS float pairs for one view's staged footpri
 constexpr int kQuarterRows = 16; // footprint rows per wave in the four-wave scan
 
 // One detector column's contribution to the K voxels of a z-run, with trans
-// weight wt.  Segment m = 0..K holds the rows whose z index
-// zh_r = tau vz_r + zc has floor k0 - 1 + m; they give (1 - fr) of their
-// value to voxel k0 - 1 + m and fr to voxel k0 + m, fr = zh_r - (k0 - 1 + m).
-// Rows are read from `col` (row r at col[(r - row0) * stride]) over
-// [rb, r1].  Segment bounds come from the inverse of the row map; a row
-// misplaced by rounding at a bound has fr within an ulp of 0 or 1, so its
-// weights are still right.  Within a segment fr grows by zstep = tau dv/dz
-// per row from the first row's fraction f_b (the projector's expression), so
-// sum fr g = f_b S + zstep sum_i i g_i over the segment's rows i = 0..n-1,
-// with S = sum g.  The second sum comes from two running sums (T += S before
-// each S += g gives T = sum (n - 1 - i) g_i, so sum i g_i = (n - 1) S - T).
-// Each segment is added to its two voxels as soon as it is complete.
+// weight wt, in second-difference form.  Segment m = 0..K holds the rows
+// whose z index zh_r lies in [k0 - 1 + m, k0 + m); they give (1 - fr) of
+// their value to voxel k0 - 1 + m and fr to voxel k0 + m,
+// fr = zh_r - (k0 - 1 + m).  With zh_r = zh_rm + zstep (r - rm) (zh_rm the
+// projector's expression for a reference row rm, zstep = tau dv/dz) and the
+// column's prefix sums X(e) = sum_{r < e} g_r, Y(e) = sum_{r < e} (r - rm) g_r
+// taken at the segment bounds e_{-1} < e_0 <= ... <= e_K, segment m has
+// S_m = X(e_m) - X(e_{m-1}) and sum fr g = coef_m S_m + zstep (Y(e_m) -
+// Y(e_{m-1})), coef_m = zh_rm - (k0 - 1 + m).  Voxel q then receives
+//   B_{q-1} - 2 B_q + B_{q+1},   B_m = (1 - coef_m) X(e_m) - zstep Y(e_m),
+// (the tent's second difference of the integrated column).  That is linear
+// in B, so the run keeps bsum_m = sum over views and columns of wt B_m
+// (m = -1..K) and forms the voxels once at the end; a constant added to X or
+// Y (another origin of the sums) changes B by a linear function of m, which
+// the second difference removes.  Bounds: e_m is the first row of z index
+// >= k0 + m, ceil((k0 + m - zc) / zstep + rc), clamped to the rows present;
+// a row misplaced by rounding at a bound has fr within an ulp of 0 or 1.
+//
+// This form reads the rows from global memory (row r at col[r * stride]),
+// summing them once from the first bound on.
 template <int K, typename P>
-__device__ __forceinline__ void column_to_run(const P* __restrict__ col, int stride, int row0,
-                                              int r1, int rb, int k0, float tau, float zstep,
-                                              float inv_s, float zc, float rc, float wt,
-                                              const float* __restrict__ vz_tab, int nv,
-                                              float (&acc)[K]) {
-  float base = (float)(k0 - 1);  // z index of segment m's lower voxel
+__device__ __forceinline__ void column_to_run(const P* __restrict__ col, int stride, int r0,
+                                              int r1, int rm, float a, float inv_s, float aw,
+                                              float wt, float bw, float (&bsum)[K + 2]) {
+  int r = min(r1 + 1, max(r0, (int)ceilf(a)));
+  float X = 0.f, Y = 0.f, w = (float)(r - rm);
+  // bsum[0] gets aw * 0 + bw * 0 at the first bound
+  aw += wt;
 #pragma unroll
   for (int m = 0; m <= K; ++m) {
-    // opaque to the optimiser, so each segment's bound and fraction are
-    // computed where they are used instead of all K + 1 being hoisted ahead
-    // of the row loops (which would hold them in registers)
-    asm volatile("" : "+v"(base));
-    const int re = min(r1 + 1, max(rb, (int)ceilf(fmaf(base + 1.f - zc, inv_s, rc))));
-    const int n = re - rb;
-    float S = 0.f, T = 0.f;
-    const P* __restrict__ gp = col + (rb - row0) * stride;
-    int i = 0;
-    for (; i + 1 < n; i += 2) {
-      const float g0 = ld(gp), g1 = ld(gp + stride);
-      gp += 2 * stride;
-      T += S;
-      S += g0;
-      T += S;
-      S += g1;
+    a += inv_s;
+    const int e = min(r1 + 1, max(r, (int)ceilf(a)));
+    for (; r < e; ++r) {
+      const float g = ld(col + (size_t)r * stride);
+      X += g;
+      Y = fmaf(w, g, Y);
+      w += 1.f;
     }
-    if (i < n) {
-      T += S;
-      S += ld(gp);
-    }
-    const float fb = fmaf(tau, vz_tab[min(rb, nv - 1)], zc) - base;
-    const float s1 = fmaf(fb, S, zstep * fmaf((float)(n - 1), S, -T));  // sum fr g
-    if (m > 0) acc[m - 1] = fmaf(wt, S - s1, acc[m - 1]);
-    if (m < K) acc[m] = fmaf(wt, s1, acc[m]);
-    rb = re;
-    base += 1.f;
+    bsum[m + 1] = fmaf(aw, X, bsum[m + 1]);
+    bsum[m + 1] = fmaf(bw, Y, bsum[m + 1]);
+    aw += wt;
   }
 }
 
@@ -103,37 +96,24 @@ __device__ __forceinline__ int minus8_add(int f, int b) {
   return r;
 }
 
-// The same contribution from the column's prefix sums, staged in LDS:
-// entry e of the column (byte offset colb + 8 e, e = r0..r1 + 1) holds
-// (sum of g over rows r0 .. e - 1, sum of (r - rm) g over the same rows),
-// rm the footprint's middle row.  A segment [b, e) has S = sum g = the
-// difference of the two entries' first parts, and with the z index of row r
-// written as zh_rm + zstep (r - rm) (zh_rm the projector's expression for
-// row rm), sum fr g = zstep (difference of the second parts) +
-// (zh_rm - base) S, base the segment's lower voxel; so no row is visited.
-// Segment bounds: the first row of z index >= k0 - 1 + m is
-// ceil((k0 - 1 + m - zc) / zstep + rc), clamped to [r0, r1 + 1] (a row
-// misplaced by rounding at a bound has fr within an ulp of 0 or 1); the
-// argument a grows by inv_s = 1 / zstep per segment.  Bounds are handled as
-// f = -e so that the clamp and the address take one instruction each.
+// The same from the column's prefix sums staged in LDS: entry e of the
+// column (byte offset colb + 8 e, e = r0..r1 + 1) holds (X(e), Y(e)) summed
+// from the footprint's first row r0.  Bounds are handled as f = -e, so that
+// the clamp and the address take one instruction each.
 template <int K>
 __device__ __forceinline__ void column_to_run_prefix(const float2* __restrict__ pre, int colb,
                                                      int nlo, int nhi, float a, float inv_s,
-                                                     float coef, float zstep, float wt,
-                                                     float (&acc)[K]) {
+                                                     float aw, float wt, float bw,
+                                                     float (&bsum)[K + 2]) {
   const char* __restrict__ base = reinterpret_cast<const char*>(pre);
-  float2 pb = *reinterpret_cast<const float2*>(base + minus8_add(clamp3(neg_ceil(a), nlo, nhi), colb));
 #pragma unroll
-  for (int m = 0; m <= K; ++m) {
-    a += inv_s;
+  for (int m = -1; m <= K; ++m) {
+    if (m >= 0) a += inv_s;
     const float2 pe =
         *reinterpret_cast<const float2*>(base + minus8_add(clamp3(neg_ceil(a), nlo, nhi), colb));
-    const float S = pe.x - pb.x;
-    const float s1 = fmaf(zstep, pe.y - pb.y, coef * S);  // sum fr g
-    if (m > 0) acc[m - 1] = fmaf(wt, S - s1, acc[m - 1]);
-    if (m < K) acc[m] = fmaf(wt, s1, acc[m]);
-    pb = pe;
-    coef -= 1.f;  // coef = zh_rm - base
+    bsum[m + 1] = fmaf(aw, pe.x, bsum[m + 1]);
+    bsum[m + 1] = fmaf(bw, pe.y, bsum[m + 1]);
+    aw += wt;
   }
 }
 
@@ -147,9 +127,7 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
   __shared__ float2 pre[kPrefTile];
   __shared__ float2 qtot[3][128];  // quarter totals of the four-wave scan
   __shared__ float cbox[2][2][8];  // projected corner columns / rows, two views
-  extern __shared__ float vz_tab[];  // vz_r = (r - (nv-1)/2) dv/dz, as the projector forms it
   const float rc = 0.5f * (float)(g.nv - 1);
-  for (int r = threadIdx.x; r < g.nv; r += blockDim.x) vz_tab[r] = ((float)r - rc) * g.dvdz;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
@@ -171,9 +149,10 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
   const float bz0 = ((float)(k0 - 1) - zc) * g.dz;
   const float bz1 = ((float)(min(g.nz, k0 + K)) - zc) * g.dz;
 
-  float acc[K];
+  // second-difference accumulators of the run (bounds k0 - 1 .. k0 + K)
+  float bsum[K + 2];
 #pragma unroll
-  for (int q = 0; q < K; ++q) acc[q] = 0.f;
+  for (int q = 0; q < K + 2; ++q) bsum[q] = 0.f;
 
   // footprint box of a view: the 8 corners of the grown voxel box
   // projected to (column, row), one corner per thread
@@ -362,12 +341,15 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     __syncthreads();  // B2
     if (!active || W <= 0 || H <= 0) continue;
     const float fp = (float)p;
+    // per column: a = the argument of the first bound's ceiling, and the
+    // weights of X and Y in wt B_m, aw = wt (1 - coef_m) from m = -1 on and
+    // bw = -wt zstep
+    const float kz = (float)(k0 - 1) - zc;
+    const float vzm = ((float)rm - rc) * g.dvdz;  // the projector's vz for row rm
     if (staged) {
       // Every column of the bracket is evaluated; one whose plane lies
       // outside 0 < tau < 1 or with no trans weight gets weight 0 (its table
       // entries are finite and its bounds are clamped into the tile).
-      const float kz = (float)(k0 - 1) - zc;
-      const float vzm = ((float)rm - rc) * g.dvdz;  // the projector's vz for row rm
       const int nlo = -(r1 + 1), nhi = -r0;
       auto column = [&](int c, const float4& h0, const int4& h1) {
         const float th = fmaf(fp, h0.y, h0.x);
@@ -376,9 +358,10 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
         const float tau = fmaf(fp, h0.w, h0.z);
         const float zstep = tau * g.dvdz;
         const float inv_s = __builtin_amdgcn_rcpf(zstep);
+        const float coef0 = fmaf(tau, vzm, zc) - (float)(k0 - 1);
         const int colb = ((c - c0) * Hp - r0) * (int)sizeof(float2);
-        column_to_run_prefix<K>(pre, colb, nlo, nhi, fmaf(kz, inv_s, rc), inv_s,
-                                fmaf(tau, vzm, zc) - (float)(k0 - 1), zstep, wt, acc);
+        column_to_run_prefix<K>(pre, colb, nlo, nhi, fmaf(kz, inv_s, rc), inv_s, -wt * coef0, wt,
+                                -wt * zstep, bsum);
       };
 #pragma unroll
       for (int q = 0; q < 3; ++q)
@@ -397,9 +380,9 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
         const float tau = fmaf(fp, h0.w, h0.z);
         const float zstep = tau * g.dvdz;
         const float inv_s = __builtin_amdgcn_rcpf(zstep);
-        const int rb = min(r1 + 1, max(r0, (int)ceilf(fmaf((float)(k0 - 1) - zc, inv_s, rc))));
-        column_to_run<K>(rview + c, g.nu, 0, r1, rb, k0, tau, zstep, inv_s, zc, rc, wt, vz_tab,
-                         g.nv, acc);
+        const float coef0 = fmaf(tau, vzm, zc) - (float)(k0 - 1);
+        column_to_run<K>(rview + c, g.nu, r0, r1, rm, fmaf(kz, inv_s, rc), inv_s, -wt * coef0,
+                         wt, -wt * zstep, bsum);
       }
     }
   }
@@ -410,7 +393,7 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     for (int q = 0; q < K; ++q) {
       if (k0 + q < g.nz) {
         const size_t o = ((size_t)(k0 + q) * g.ny + j) * g.nx + i;
-        st(vol + o, acc[q]);
+        st(vol + o, fmaf(-2.f, bsum[q + 1], bsum[q] + bsum[q + 2]));
         if (partials) {
           const float sv = ld(vol + o);
           part += (double)sv * (double)sv;
@@ -436,8 +419,7 @@ hipError_t launch_backproject(const GeomDev& g, const ViewInfo* views, const Col
   dim3 block(256);
   dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kZRun - 1) / kZRun);
   if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
-  const size_t lds = sizeof(float) * (size_t)g.nv;
-  hipLaunchKernelGGL((k_backproject<T, kZRun>), grid, block, lds, s, g, views, cols, rl, vol,
+  hipLaunchKernelGGL((k_backproject<T, kZRun>), grid, block, 0, s, g, views, cols, rl, vol,
                      partials);
   return hipGetLastError();
 }
