@@ -502,7 +502,7 @@ static RowPlan row_plan(const GeomDev& g) {
   const double hx = (0.5 * g.nx + 2.0) * g.dx, hy = (0.5 * g.ny + 2.0) * g.dy;
   const double tau_max = ((double)g.sad + std::sqrt(hx * hx + hy * hy)) / (double)g.sdd;
   const double row_span = (double)g.dvdz * tau_max;
-  const RowPlan cand[] = {{16, 6}, {8, 4}, {8, 6}, {4, 3}, {4, 4}, {2, 3}};
+  const RowPlan cand[] = {{16, 6}, {8, 4}, {8, 6}, {8, 7}, {4, 3}, {4, 4}, {2, 3}};
   for (const RowPlan& c : cand)
     if (std::ceil((c.rpt - 1) * row_span + 0.05) + 2.0 <= (double)c.nl) return c;
   return {1, 2};
@@ -539,8 +539,11 @@ static void launch_project_mode(const GeomDev& g, const ViewInfo* views, const C
   else if (rp.rpt == 8 && rp.nl == 4)
     launch_project_rows<T, MODE, 8, 4>(g, views, cols, padN, padT, gin, out, rl, partials,
                                        n_partials, s);
-  else if (rp.rpt == 8)
+  else if (rp.rpt == 8 && rp.nl == 6)
     launch_project_rows<T, MODE, 8, 6>(g, views, cols, padN, padT, gin, out, rl, partials,
+                                       n_partials, s);
+  else if (rp.rpt == 8)
+    launch_project_rows<T, MODE, 8, 7>(g, views, cols, padN, padT, gin, out, rl, partials,
                                        n_partials, s);
   else if (rp.rpt == 4 && rp.nl == 3)
     launch_project_rows<T, MODE, 4, 3>(g, views, cols, padN, padT, gin, out, rl, partials,

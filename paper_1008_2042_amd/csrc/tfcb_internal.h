@@ -44,7 +44,7 @@ inline size_t dtype_size(tfcb_dtype dt) { return dt == TFCB_F32 ? 4 : 2; }
 // in the loop.  "native" copy: ns = ny, nt = nx (y-stepping views);
 // "transposed" copy: ns = nx, nt = ny (x-stepping views).  Only the interior
 // is ever written; the pads are cleared once per call.
-constexpr int kZPad = 5;
+constexpr int kZPad = 6;
 constexpr int kPadLead = 4;
 __host__ __device__ __forceinline__ int pad_row(int nt) { return (nt + 1 + 3) & ~3; }
 inline size_t pad_elems(int ns, int nt, int nz) {
