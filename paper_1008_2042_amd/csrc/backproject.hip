@@ -13,7 +13,7 @@
 // each such column the rows follow from the z index of the row.  The
 // projections are prescaled by l (rl = l * g) once per application.
 //
-// Mapping: 256-thread blocks of 64 (x) x 4 (y) voxel columns; each thread
+// Mapping: 256-thread blocks of kBX (x) x kBY (y) voxel columns; each thread
 // accumulates a run of K voxels along z.  Per view the block first stages
 // its whole detector footprint (the bounding box of the projection of its
 // voxel box grown by one voxel, the support of the hat weights) into LDS as
@@ -31,6 +31,12 @@ namespace tfcb {
 constexpr int kZRun = 8;        // voxels per thread along z
 constexpr int kPrefTile = 5120; // LDS float pairs for one view's staged footprint (40 KB)
 constexpr int kQuarterRows = 16; // footprint rows per wave in the four-wave scan
+// voxel columns of a block: 16 x 16 keeps the footprint of a view smaller
+// than 64 x 4 would (about half the area at the paper's geometry, and at
+// most 60 detector columns at the 512 x 512 x 256 geometry, so one 64-column
+// chunk of the scan)
+constexpr int kBX = 16, kBY = 16;
+static_assert(kBX * kBY == 256 && 64 % kBX == 0, "block shape");
 
 // One detector column's contribution to the K voxels of a z-run, with trans
 // weight wt, in second-difference form.  Segment m = 0..K holds the rows
@@ -130,8 +136,8 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
   const float rc = 0.5f * (float)(g.nv - 1);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
-  const int j = blockIdx.y * 4 + wave;
+  const int i = blockIdx.x * kBX + (int)(threadIdx.x % kBX);
+  const int j = blockIdx.y * kBY + (int)(threadIdx.x / kBX);
   const int k0 = blockIdx.z * K;
   const bool active = i < g.nx && j < g.ny;
   const float xc = 0.5f * (float)(g.nx - 1), yc = 0.5f * (float)(g.ny - 1);
@@ -141,11 +147,11 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
   const float X = ((float)i - xc) * g.dx, Y = ((float)j - yc) * g.dy;
   // the block's voxel box grown by one voxel on every side (mm); signed
   // arithmetic: the first block's lower bound is index -1
-  const int bi = (int)blockIdx.x * 64, bj = (int)blockIdx.y * 4;
+  const int bi = (int)blockIdx.x * kBX, bj = (int)blockIdx.y * kBY;
   const float bx0 = ((float)(bi - 1) - xc) * g.dx;
-  const float bx1 = ((float)min(g.nx, bi + 64) - xc) * g.dx;
+  const float bx1 = ((float)min(g.nx, bi + kBX) - xc) * g.dx;
   const float by0 = ((float)(bj - 1) - yc) * g.dy;
-  const float by1 = ((float)min(g.ny, bj + 4) - yc) * g.dy;
+  const float by1 = ((float)min(g.ny, bj + kBY) - yc) * g.dy;
   const float bz0 = ((float)(k0 - 1) - zc) * g.dz;
   const float bz1 = ((float)(min(g.nz, k0 + K)) - zc) * g.dz;
 
@@ -409,7 +415,7 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
 }
 
 int backproject_num_blocks(const GeomDev& g) {
-  return ((g.nx + 63) / 64) * ((g.ny + 3) / 4) * ((g.nz + kZRun - 1) / kZRun);
+  return ((g.nx + kBX - 1) / kBX) * ((g.ny + kBY - 1) / kBY) * ((g.nz + kZRun - 1) / kZRun);
 }
 
 template <typename T>
@@ -417,7 +423,7 @@ hipError_t launch_backproject(const GeomDev& g, const ViewInfo* views, const Col
                               const T* rl, T* vol, double* partials, int* n_partials,
                               hipStream_t s) {
   dim3 block(256);
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kZRun - 1) / kZRun);
+  dim3 grid((g.nx + kBX - 1) / kBX, (g.ny + kBY - 1) / kBY, (g.nz + kZRun - 1) / kZRun);
   if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
   hipLaunchKernelGGL((k_backproject<T, kZRun>), grid, block, 0, s, g, views, cols, rl, vol,
                      partials);
