@@ -29,7 +29,9 @@
 namespace tfcb {
 
 constexpr int kZRun = 8;        // voxels per thread along z
-constexpr int kPrefTile = 5120; // LDS float pairs for one view's staged footprint (40 KB)
+constexpr int kPrefTile = 4096; // LDS float pairs for one view's staged footprint (32 KB)
+constexpr int kChunks = 1;      // 64-column chunks of the four-wave scan
+constexpr int kPrefCols = 1;    // bracket columns whose table records are fetched before the scan
 constexpr int kQuarterRows = 16; // footprint rows per wave in the four-wave scan
 // voxel columns of a block: 16 x 16 keeps the footprint of a view smaller
 // than 64 x 4 would (about half the area at the paper's geometry, and at
@@ -124,14 +126,14 @@ __device__ __forceinline__ void column_to_run_prefix(const float2* __restrict__ 
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
+__global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInfo* __restrict__ views,
                                                      const ColInfo* __restrict__ cols,
                                                      const T* __restrict__ rl,
                                                      T* __restrict__ vol,
                                                      double* __restrict__ partials) {
   __shared__ double red[4];
   __shared__ float2 pre[kPrefTile];
-  __shared__ float2 qtot[3][128];  // quarter totals of the four-wave scan
+  __shared__ float2 qtot[3][kChunks * 64];  // quarter totals of the four-wave scan
   __shared__ float cbox[2][2][8];  // projected corner columns / rows, two views
   const float rc = 0.5f * (float)(g.nv - 1);
 
@@ -211,17 +213,17 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     // wave's totals).  Other footprints: stride (H + 1) | 1, scanned a
     // column per lane.
     const int Hq = 16 * ((H + 15) >> 4) + 1;
-    const bool quarters = W > 0 && H > 0 && W <= 2 * 64 && H <= 4 * kQuarterRows &&
+    const bool quarters = W > 0 && H > 0 && W <= kChunks * 64 && H <= 4 * kQuarterRows &&
                           W * Hq <= kPrefTile;
     const int Hp = quarters ? Hq : ((H + 1) | 1);
     const bool staged = quarters || (W > 0 && H > 0 && W * Hp <= kPrefTile);
     const int q0 = kQuarterRows * wv;
     const bool qrows = quarters && q0 < H;  // this wave has rows to scan
     const float wq = (float)(r0 + q0 - rm);  // row offset of the quarter's first row
-    float qv[2][kQuarterRows];
+    float qv[kChunks][kQuarterRows];
     if (qrows) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kChunks; ++h) {
         if (h == 1 && W <= 64) break;
         // a scalar row pointer stepped down the rows, a 32-bit column offset per lane
         const uint32_t cb = (uint32_t)(min(lane + 64 * h, W - 1) * sizeof(T));
@@ -269,10 +271,10 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     const int clo = !active ? 1 : max(c0, (int)floorf(fminf(ca, cbc) - 1e-3f) + 1);
     const int chi = !active ? 0 : min(c1, (int)ceilf(fmaxf(ca, cbc) + 1e-3f) - 1);
     const ColInfo* __restrict__ cview = cols + (size_t)view * g.nu;
-    float4 pf0[3];
-    int4 pf1[3];
+    float4 pf0[kPrefCols];
+    int4 pf1[kPrefCols];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kPrefCols; ++q) {
       const int c = min(clo + q, g.nu - 1);
       if (clo + q <= chi) {
         pf0[q] = reinterpret_cast<const float4*>(cview + c)[0];
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     }
     if (qrows && wv < 3) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kChunks; ++h) {
         if (h == 1 && W <= 64) break;
         float s0 = 0.f, s1 = 0.f, w = wq;
 #pragma unroll
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
     if (view + 1 < g.n_views) corners(view + 1, cb ^ 1);
     if (qrows) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kChunks; ++h) {
         if (h == 1 && W <= 64) break;
         const int cc = lane + 64 * h;
         if (cc < W) {
@@ -370,9 +372,9 @@ __global__ __launch_bounds__(256, 3) void k_backproject(GeomDev g, const ViewInf
                                 -wt * zstep, bsum);
       };
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+      for (int q = 0; q < kPrefCols; ++q)
         if (clo + q <= chi) column(clo + q, pf0[q], pf1[q]);
-      for (int c = clo + 3; c <= chi; ++c)
+      for (int c = clo + kPrefCols; c <= chi; ++c)
         column(c, reinterpret_cast<const float4*>(cview + c)[0],
                reinterpret_cast<const int4*>(cview + c)[1]);
     } else {
