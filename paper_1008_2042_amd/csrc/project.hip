@@ -63,11 +63,24 @@ __device__ __forceinline__ void plane_range(const ColInfo& ci, float vz, float z
   while (hi >= lo && !sample_inside(ci, hi, vz, zc, nt, nz)) --hi;
 }
 
+// Levels that rows j..RPT-1 can still use, counted from row j's lower
+// level: the host's row plan keeps the rows' z span within
+// (RPT - 1) rs + 0.05 <= NL - 2 slices, so rows j..RPT-1 span at most
+// (RPT - 1 - j) (NL - 2.05) / (RPT - 1) slices, and floor(zh_k) -
+// floor(zh_j) is at most the ceiling of that.
+template <int RPT, int NL>
+__host__ __device__ constexpr int levels_needed(int j) {
+  return RPT == 1 ? 2
+                  : 2 + ((RPT - 1 - j) * (100 * NL - 205) + 100 * (RPT - 1) - 1) /
+                            (100 * (RPT - 1));
+}
+
 // Row j's bilinear sample from the trans-interpolated levels: the two levels
 // around its z index, d_j = floor(zh_j) - floor(zh_0) and d_j + 1.  The
 // rows' z indices rise with j by less than one slice per row, so d_j is
 // d_{j-1} or d_{j-1} + 1: the pair is carried along as a shift register of
-// the levels, which moves on where floor(zh_j) exceeds floor(zh_{j-1}).
+// the levels, which moves on where floor(zh_j) exceeds floor(zh_{j-1}).  At
+// row j only the levels_needed(j) entries that later rows can reach move.
 template <int RPT, int NL>
 __device__ __forceinline__ void rows_from_levels(const float (&lev)[NL], const float (&zh)[RPT],
                                                  const float (&zf)[RPT], float (&acc)[RPT]) {
@@ -78,11 +91,15 @@ __device__ __forceinline__ void rows_from_levels(const float (&lev)[NL], const f
   for (int j = 0; j < RPT; ++j) {
     if (j > 0 && zf[j] > zf[j - 1]) {
 #pragma unroll
-      for (int l = 0; l + 1 < NL; ++l) win[l] = win[l + 1];
+      for (int l = 0; l + 1 < NL; ++l)
+        if (l < levels_needed<RPT, NL>(j)) win[l] = win[l + 1];
     }
     acc[j] += fmaf(zh[j] - zf[j], win[1] - win[0], win[0]);
   }
 }
+static_assert(levels_needed<16, 6>(0) == 6 && levels_needed<16, 6>(15) == 2 &&
+                  levels_needed<8, 7>(0) == 7 && levels_needed<4, 4>(3) == 2,
+              "level window");
 
 // The samples of plane p for the RPT rows of one column (row j's z factor
 // vz[j], increasing in j).  The padded copy `vb` points at element
