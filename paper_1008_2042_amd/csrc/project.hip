@@ -76,25 +76,27 @@ __host__ __device__ constexpr int levels_needed(int j) {
 }
 
 // Row j's bilinear sample from the trans-interpolated levels: the two levels
-// around its z index, d_j = floor(zh_j) - floor(zh_0) and d_j + 1.  The
-// rows' z indices rise with j by less than one slice per row, so d_j is
-// d_{j-1} or d_{j-1} + 1: the pair is carried along as a shift register of
-// the levels, which moves on where floor(zh_j) exceeds floor(zh_{j-1}).  At
-// row j only the levels_needed(j) entries that later rows can reach move.
+// around its z index, d_j = floor(zh_j) - floor(zh_0) and d_j + 1, weighted
+// by the fraction fr_j = zh_j - floor(zh_j).  The rows' z indices rise with j
+// by more than 0 and less than one slice per row, so d_j is d_{j-1} or
+// d_{j-1} + 1, and it is d_{j-1} + 1 exactly where the fraction wraps,
+// fr_j < fr_{j-1}: the pair is carried along as a shift register of the
+// levels, which moves on there.  At row j only the levels_needed(j) entries
+// that later rows can reach move.
 template <int RPT, int NL>
-__device__ __forceinline__ void rows_from_levels(const float (&lev)[NL], const float (&zh)[RPT],
-                                                 const float (&zf)[RPT], float (&acc)[RPT]) {
+__device__ __forceinline__ void rows_from_levels(const float (&lev)[NL], const float (&fr)[RPT],
+                                                 float (&acc)[RPT]) {
   float win[NL];
 #pragma unroll
   for (int l = 0; l < NL; ++l) win[l] = lev[l];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    if (j > 0 && zf[j] > zf[j - 1]) {
+    if (j > 0 && fr[j] < fr[j - 1]) {
 #pragma unroll
       for (int l = 0; l + 1 < NL; ++l)
         if (l < levels_needed<RPT, NL>(j)) win[l] = win[l + 1];
     }
-    acc[j] += fmaf(zh[j] - zf[j], win[1] - win[0], win[0]);
+    acc[j] += fmaf(fr[j], win[1] - win[0], win[0]);
   }
 }
 static_assert(levels_needed<16, 6>(0) == 6 && levels_needed<16, 6>(15) == 2 &&
@@ -121,13 +123,10 @@ __device__ __forceinline__ void sample_rows(const T* __restrict__ vb, const ColI
   // guarantee in-buffer addresses
   const int it = min(max((int)tf, -1), nt - 1);
   const float wt = th - tf;
-  float zh[RPT], zf[RPT];
+  float fr[RPT];  // z fractions, v_fract (the hardware's x - floor(x))
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    zh[j] = z_index(ci, p, vz[j], zc);
-    zf[j] = floorf(zh[j]);
-  }
-  const int iz0 = min(max((int)zf[0], -kZPad), nz - 1);
+  for (int j = 0; j < RPT; ++j) fr[j] = __builtin_amdgcn_fractf(z_index(ci, p, vz[j], zc));
+  const int iz0 = min(max((int)floorf(z_index(ci, p, vz[0], zc)), -kZPad), nz - 1);
   const T* __restrict__ q = vb + ((iz0 * ns + p) * ntp + it);
   float lev[NL];
 #pragma unroll
@@ -135,7 +134,7 @@ __device__ __forceinline__ void sample_rows(const T* __restrict__ vb, const ColI
     const float v0 = ld(q + l * zs), v1 = ld(q + l * zs + 1);
     lev[l] = fmaf(wt, v1 - v0, v0);
   }
-  rows_from_levels<RPT, NL>(lev, zh, zf, acc);
+  rows_from_levels<RPT, NL>(lev, fr, acc);
 }
 
 template <typename T, int MODE, int RPT, int NL, int PU = 2>
@@ -299,13 +298,10 @@ __device__ __forceinline__ void sample_rows_lds(const float* __restrict__ tile, 
   const float tf = floorf(th);
   const int it = min(max((int)tf, -1), nt - 1);
   const float wt = th - tf;
-  float zh[RPT], zf[RPT];
+  float fr[RPT];  // z fractions, v_fract (the hardware's x - floor(x))
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    zh[j] = z_index(ci, p, vz[j], zc);
-    zf[j] = floorf(zh[j]);
-  }
-  const int iz0 = min(max((int)zf[0], -kZPad), nz - 1);
+  for (int j = 0; j < RPT; ++j) fr[j] = __builtin_amdgcn_fractf(z_index(ci, p, vz[j], zc));
+  const int iz0 = min(max((int)floorf(z_index(ci, p, vz[0], zc)), -kZPad), nz - 1);
   const float* __restrict__ q = tile + (iz0 - b.zl) * (4 * kStageF4) + (it - b.tl4);
   float lev[NL];
 #pragma unroll
@@ -313,7 +309,7 @@ __device__ __forceinline__ void sample_rows_lds(const float* __restrict__ tile, 
     const float v0 = q[l * 4 * kStageF4], v1 = q[l * 4 * kStageF4 + 1];
     lev[l] = fmaf(wt, v1 - v0, v0);
   }
-  rows_from_levels<RPT, NL>(lev, zh, zf, acc);
+  rows_from_levels<RPT, NL>(lev, fr, acc);
 }
 
 template <typename T, int MODE, int RPT, int NL>
