@@ -416,7 +416,6 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomDev g, const ViewInf
       }
       return b;
     };
-    typename Raw4<T>::type reg[kStageRegs];
     // this thread's (level row, vector) slots of the box and their offsets
     // from the box's first element; per plane only the first element moves
     const int zs = ns * pad_row(nt);
@@ -428,36 +427,52 @@ __global__ __launch_bounds__(256) void k_project_staged(GeomDev g, const ViewInf
       sq4[k] = e % kStageF4;
       soff[k] = srow[k] * zs + 4 * sq4[k];
     }
-    auto stage_load = [&](const StageBox& b, int p) {
-      const T* __restrict__ first = base + pad_index(ns, nt, b.zl, p, b.tl4);
+    // Two register sets, so that a plane's loads are issued two planes
+    // before its data go to LDS: iteration p issues plane p + 2's loads into
+    // one set, samples plane p and stores plane p + 1 (loaded an iteration
+    // earlier) from the other set into the tile buffer plane p - 1 used.
+    using Raw = typename Raw4<T>::type;
+    auto stage_load = [&](Raw (&r)[kStageRegs], int p) {
+      const StageBox b = get_box(p);
+      // the box's first vector; a non-empty box lies in the buffer, and the
+      // clamp keeps an empty one's there too
+      const int zl = min(max(b.zl, -kZPad), nz + kZPad - 1);
+      const int tl4 = min(max(b.tl4, -4), pad_row(nt) - 4);
+      const T* __restrict__ first = base + pad_index(ns, nt, zl, p, tl4);
+      // a slot outside the box loads the box's first vector instead (in
+      // bounds; the samples read only inside the box), so no load is
+      // conditional
 #pragma unroll
       for (int k = 0; k < kStageRegs; ++k)
-        reg[k] = (srow[k] < b.nzr && sq4[k] < b.nf4) ? ld_raw4(first + soff[k]) : raw4_zero<T>();
+        r[k] = ld_raw4(first + ((srow[k] < b.nzr && sq4[k] < b.nf4) ? soff[k] : 0));
     };
-    auto stage_store = [&](int buf) {
+    auto stage_store = [&](const Raw (&r)[kStageRegs], int buf) {
 #pragma unroll
       for (int k = 0; k < kStageRegs; ++k) {
         const int e = threadIdx.x + 256 * k;
-        if (e < kStageRows * kStageF4) tile[buf][e] = widen4<T>(reg[k]);
+        if (e < kStageRows * kStageF4) tile[buf][e] = widen4<T>(r[k]);
       }
     };
-    StageBox bcur = get_box(LO);
-    stage_load(bcur, LO);
-    stage_store(0);
+    Raw regA[kStageRegs], regB[kStageRegs];
+    stage_load(regA, LO);
+    stage_store(regA, 0);
+    stage_load(regB, min(LO + 1, HI));
     __syncthreads();
-    for (int p = LO; p <= HI; ++p) {
+    // Loads and stores are unconditional (past HI the last plane is loaded
+    // again and stored into the buffer no later plane reads), so that no
+    // branch separates them and only the older set's loads are waited for.
+    auto step = [&](int p, Raw (&ld_set)[kStageRegs], const Raw (&st_set)[kStageRegs]) {
       const int cur = (p - LO) & 1;
-      StageBox bnext;
-      if (p < HI) {
-        bnext = get_box(p + 1);
-        stage_load(bnext, p + 1);
-      }
+      stage_load(ld_set, min(p + 2, HI));
       if (p >= lo && p <= hi)
-        sample_rows_lds<RPT, NL>(reinterpret_cast<const float*>(tile[cur]), bcur, ci, p, vz, zc,
-                                 nt, nz, acc0);
-      if (p < HI) stage_store(cur ^ 1);
+        sample_rows_lds<RPT, NL>(reinterpret_cast<const float*>(tile[cur]), get_box(p), ci, p, vz,
+                                 zc, nt, nz, acc0);
+      stage_store(st_set, cur ^ 1);
       __syncthreads();
-      bcur = bnext;
+    };
+    for (int p = LO; p <= HI; p += 2) {
+      step(p, regA, regB);
+      if (p + 1 <= HI) step(p + 1, regB, regA);
     }
   } else if (active) {
     const int ntp = pad_row(nt), zs = ns * ntp;
