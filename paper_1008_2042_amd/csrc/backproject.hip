@@ -285,15 +285,15 @@ __global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInf
 #pragma unroll
       for (int h = 0; h < kChunks; ++h) {
         if (h == 1 && W <= 64) break;
-        float s0 = 0.f, s1 = 0.f, w = wq;
+        // sum (wq + u) v = wq sum v + sum u v
+        float s0 = 0.f, su = 0.f;
 #pragma unroll
         for (int u = 0; u < kQuarterRows; ++u) {
           s0 += qv[h][u];
-          s1 = fmaf(w, qv[h][u], s1);
-          w += 1.f;
+          su = fmaf((float)u, qv[h][u], su);
         }
         const int cc = lane + 64 * h;
-        if (cc < W) qtot[wv][cc] = make_float2(s0, s1);
+        if (cc < W) qtot[wv][cc] = make_float2(s0, fmaf(wq, s0, su));
       }
     }
     __syncthreads();  // B1
