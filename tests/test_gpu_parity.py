@@ -82,7 +82,11 @@ def test_project_parity(g):
     assert rel(got, want) <= 1e-4
 
 
-@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE], ids=["tiny", "ragged", "degenerate"])
+# ROWS16's footprints take both LDS paths of the backprojector (the
+# four-wave quarter scan and the column-per-lane scan) and include blocks
+# whose footprint lies off the detector for some views
+@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE, ROWS16],
+                         ids=["tiny", "ragged", "degenerate", "rows16"])
 def test_backproject_parity(g):
     dev = _dev()
     y = inputs.random_sino(g, 2)
@@ -103,9 +107,9 @@ def test_backproject_parity_large_footprint():
     assert rel(got, oracle.backproject(g, y)) <= 1e-4
 
 
-def test_adjoint_identity_gpu():
+@pytest.mark.parametrize("g", [RAGGED, ROWS16], ids=["ragged", "rows16"])
+def test_adjoint_identity_gpu(g):
     dev = _dev()
-    g = RAGGED
     f = inputs.random_volume(g, 3)
     y = inputs.random_sino(g, 4)
     announce("adjoint identity")
