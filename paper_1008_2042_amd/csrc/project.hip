@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
 constexpr int kStageF4 = 32;    // 4-element vectors per staged level row
 constexpr int kStageRows = 24;  // level rows per staged plane
 constexpr int kStageRegs = (kStageRows * kStageF4 + 255) / 256;
-constexpr int kStageBoxes = 1024;  // planes whose boxes a block tabulates in LDS
+constexpr int kStageBoxes = 512;  // planes whose boxes a block tabulates in LDS (8 KB)
 
 // Four consecutive stored elements, loaded as they are stored (a float4, or
 // 8 bytes of FP16/BF16) and widened to FP32 only when written to LDS, so
@@ -313,7 +313,9 @@ __device__ __forceinline__ void sample_rows_lds(const float* __restrict__ tile, 
 }
 
 template <typename T, int MODE, int RPT, int NL>
-__global__ __launch_bounds__(256) void k_project_staged(GeomDev g, const ViewInfo* __restrict__ views,
+// Plans of at most 8 rows fit 128 VGPRs: four waves per SIMD (and four blocks
+// per CU within LDS).
+__global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev g, const ViewInfo* __restrict__ views,
                                                         const ColInfo* __restrict__ cols,
                                                         const T* __restrict__ padN,
                                                         const T* __restrict__ padT,
@@ -531,8 +533,14 @@ static RowPlan row_plan(const GeomDev& g) {
   const double tau_max = ((double)g.sad + std::sqrt(hx * hx + hy * hy)) / (double)g.sdd;
   const double row_span = (double)g.dvdz * tau_max;
   const RowPlan cand[] = {{16, 6}, {8, 4}, {8, 6}, {8, 7}, {4, 3}, {4, 4}, {2, 3}};
+  // 16 rows per thread only when its grid fills the chip a few times over
+  // (about 768 blocks run at once); a smaller grid (the coarse level of the
+  // multigrid) takes the first 8-row plan that fits, twice the blocks
+  const long blocks16 = (long)((g.nu + 63) / 64) * ((g.nv + 63) / 64) * g.n_views;
+  const bool small = blocks16 < 1536;
   for (const RowPlan& c : cand)
-    if (std::ceil((c.rpt - 1) * row_span + 0.05) + 2.0 <= (double)c.nl) return c;
+    if (std::ceil((c.rpt - 1) * row_span + 0.05) + 2.0 <= (double)c.nl && !(small && c.rpt > 8))
+      return c;
   return {1, 2};
 }
 

@@ -55,13 +55,19 @@ RAGGED = Geometry(70, 45, 9, 0.9, 1.1, 1.7, 150, 37, 0.8, 1.3, sad=300.0, sdd=45
                   angles=np.array([0.0, math.pi / 4, 1.0, 2.0, 3.0 * math.pi / 4, 4.0, 5.9]))
 DEGENERATE = Geometry(1, 3, 1, 1.0, 1.0, 1.0, 5, 1, 1.0, 1.0, sad=50.0, sdd=75.0, n_views=1)
 # the ragged geometry with finer detector rows than slices: the projector
-# then takes 16 rows per thread with 6 z levels per plane (dv/dz = 0.16),
-# 8 rows with 4 levels (0.35), 8 rows with 6 levels (0.4) and 8 rows with 7
-# levels (0.85); the row counts 75 and 61 leave ragged row tails in every
-# block
+# then takes 16 rows per thread with 6 z levels per plane where its grid is
+# large (dv/dz = 0.16, ROWS16_MANY; with 7 views the grid is small and it
+# takes 8 rows with 4 levels), 8 rows with 4 levels (0.35), 8 rows with 6
+# levels (0.4) and 8 rows with 7 levels (0.85); the row counts 75 and 61
+# leave ragged row tails in every block
 _RAGGED_ANGLES = np.array([0.0, math.pi / 4, 1.0, 2.0, 3.0 * math.pi / 4, 4.0, 5.9])
 ROWS16 = Geometry(70, 45, 21, 0.9, 1.1, 2.5, 150, 75, 0.8, 0.4, sad=300.0, sdd=450.0, n_views=7,
                   angles=_RAGGED_ANGLES)
+# the projector keeps 16-row threads only for grids of at least 1536 blocks
+# of 64 x 64 rays (a smaller grid takes an 8-row plan for more blocks): the
+# same geometry with 256 views runs the 16-row plan
+ROWS16_MANY = Geometry(70, 45, 21, 0.9, 1.1, 2.5, 150, 75, 0.8, 0.4, sad=300.0, sdd=450.0,
+                       n_views=256)
 ROWS8N4 = Geometry(70, 45, 13, 0.9, 1.1, 2.0, 150, 61, 0.8, 0.7, sad=300.0, sdd=450.0, n_views=7,
                    angles=_RAGGED_ANGLES)
 ROWS8N6 = Geometry(70, 45, 13, 0.9, 1.1, 2.0, 150, 61, 0.8, 0.8, sad=300.0, sdd=450.0, n_views=7,
@@ -70,9 +76,10 @@ ROWS8N7 = Geometry(70, 45, 13, 0.9, 1.1, 1.0, 150, 61, 0.8, 0.85, sad=300.0, sdd
                    angles=_RAGGED_ANGLES)
 
 
-@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE, ROWS16, ROWS8N4, ROWS8N6, ROWS8N7],
-                         ids=["tiny", "ragged", "degenerate", "rows16", "rows8n4", "rows8n6",
-                              "rows8n7"])
+@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE, ROWS16, ROWS16_MANY, ROWS8N4, ROWS8N6,
+                               ROWS8N7],
+                         ids=["tiny", "ragged", "degenerate", "rows16", "rows16_many", "rows8n4",
+                              "rows8n6", "rows8n7"])
 def test_project_parity(g):
     dev = _dev()
     f = inputs.random_volume(g, 1)
