@@ -225,11 +225,11 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
 // 0.01 for rounding: z levels from the lowest row's floor to the stack top of
 // the last wave's first row, trans positions from the lower corner's floor
 // down to a 4-element boundary up to the upper corner's floor + 1.  The box's
-// level rows are loaded with aligned 4-element vector loads (each needed
-// line once per block and plane) into one of two LDS buffers while the
-// threads sample the other one, so a plane costs one barrier.  A block whose
-// box can exceed the buffers on any of its planes takes the direct path of
-// k_project instead.
+// level rows are loaded two planes ahead with aligned 4-element vector loads
+// (each needed line once per block and plane) into registers, and stored
+// into one of two LDS buffers while the threads sample the other one, so a
+// plane costs one barrier.  A block whose box can exceed the buffers on any
+// of its planes takes the direct path of k_project instead.
 constexpr int kStageF4 = 32;    // 4-element vectors per staged level row
 constexpr int kStageRows = 24;  // level rows per staged plane
 constexpr int kStageRegs = (kStageRows * kStageF4 + 255) / 256;
