@@ -15,16 +15,23 @@
 //
 // Mapping: a block owns an HX x HY tile of (x, y) positions (one thread
 // each) = the output tile plus a halo of d, and marches along z over a chunk
-// of output slices.  Per step za it
-//   1. stages input slice za + d (tile + 2d halo, reflected indices) into an
-//      LDS ring of 2d+1 slices;
-//   2. computes the 27 coefficients at (x, y, za) separably from the ring,
-//      shrinks the 26 high bands by max(1 - lambda/||alpha_h||, 0);
-//   3. folds them along z into 9 partial sums c_lm for output slices
-//      za - d, za, za + d (an LDS ring of accumulators, one per position);
-//   4. when slice za - d is complete, correlates its 9 partial sums in x and y
-//      for the interior positions and writes the voxel, with H and the
-//      momentum epilogue.
+// of output slices, one chain per residue of z modulo d (with dilation d the
+// three slices a coefficient or an output reads are d apart, so the residue
+// classes never mix).  Per step of a chain (slice zs = za + d) a thread
+//   1. filters the staged slice zs in x and y at its position (9 LDS reads),
+//      giving the 9 xy bands b_lm of that slice;
+//   2. filters in z the b of slices za - d, za, za + d held in registers,
+//      giving the 27 coefficients at (x, y, za), and shrinks the 26 high bands
+//      by max(1 - lambda/||alpha_h||, 0);
+//   3. folds them along z into register accumulators c_lm of output slices
+//      za - d, za, za + d, after which slice za - d is complete;
+//   4. writes the next slice (loaded into registers at the start of the step)
+//      to the other LDS buffer, and, when za - d is an output slice,
+//      correlates its c_lm in y (27 LDS reads) and then in x (9 reads) for the
+//      interior positions and writes the voxel, with H and the momentum
+//      epilogue.
+// b and c rotate through three register sets (the loop is unrolled three
+// times), so nothing moves between registers; a step costs two barriers.
 #include "tfcb_internal.h"
 
 namespace tfcb {
@@ -57,19 +64,34 @@ __device__ __forceinline__ float corr3(int l, float cm, float c0, float cp) {
 
 }  // namespace
 
+// The xy bands of one staged slice at (tx, ty): x filter of rows y - d, y,
+// y + d, then y filter; b[3m + l] = h_m (y) h_l (x).
+template <int D, int FX, int FY>
+__device__ __forceinline__ void xy_bands(const float (&sl)[FY][FX], int tx, int ty, float (&b)[9]) {
+  float a[3][3];  // a[row][l]: x-filtered rows y - d, y, y + d
+#pragma unroll
+  for (int ry = 0; ry < 3; ++ry) {
+    const int fy = ty + D + (ry - 1) * D;
+    conv3(sl[fy][tx], sl[fy][tx + D], sl[fy][tx + 2 * D], a[ry][0], a[ry][1], a[ry][2]);
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) conv3(a[0][l], a[1][l], a[2][l], b[l], b[3 + l], b[6 + l]);
+}
+
 template <typename T, int D, int HX, int HY, bool HAS_LOW, bool MOM>
-__global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int zchunk,
+__global__ __launch_bounds__(HX* HY, HAS_LOW ? 3 : 4) void k_framelet(int nx, int ny, int nz, int zchunk,
                                                       float lambda, int positivity,
                                                       const T* __restrict__ in,
                                                       const T* __restrict__ low,
                                                       T* __restrict__ out,
                                                       const T* __restrict__ fcur,
                                                       T* __restrict__ vnext, float mom) {
-  constexpr int M = 2 * D + 1;          // ring depth
   constexpr int FX = HX + 2 * D, FY = HY + 2 * D;
   constexpr int NT = HX * HY;
-  __shared__ float fring[M][FY][FX];
-  __shared__ float cacc[M][9][HY][HX];
+  constexpr int NS = (FX * FY + NT - 1) / NT;  // staged elements per thread
+  __shared__ float sbuf[2][FY][FX];
+  __shared__ float cbuf[9][HY][HX];
+  __shared__ float colbuf[3][HY][HX];
 
   const int tx = threadIdx.x % HX, ty = threadIdx.x / HX;
   const int ox = blockIdx.x * (HX - 2 * D);  // first output x of the tile
@@ -78,117 +100,147 @@ __global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int
   const int z_end = min(nz, z_begin + zchunk);
   // this thread's position (may be a halo position outside the grid)
   const int px = ox + tx - D, py = oy + ty - D;
+  const bool interior = tx >= D && tx < HX - D && ty >= D && ty < HY - D;
+  const bool ycorr = ty >= D && ty < HY - D;
+  const bool writer = interior && px < nx && py < ny;
+  const size_t plane = (size_t)nx * ny;
 
-  auto stage = [&](int zs) {
-    const int slot = ((zs % M) + M) % M;
-    const int zr = reflect_idx(zs, nz);
-    for (int e = threadIdx.x; e < FX * FY; e += NT) {
-      const int fx = e % FX, fy = e / FX;
-      const int gx = reflect_idx(ox - 2 * D + fx, nx);
-      const int gy = reflect_idx(oy - 2 * D + fy, ny);
-      fring[slot][fy][fx] = ld(in + ((size_t)zr * ny + gy) * nx + gx);
-    }
-  };
-  for (int s = 0; s < M; ++s)
-    for (int q = 0; q < 9; ++q) cacc[s][q][ty][tx] = 0.f;
-  for (int zs = z_begin - 2 * D; zs < z_begin; ++zs) stage(zs);
+  // staged elements of this thread: in-plane offsets (reflected) and LDS slots
+  int soff[NS], sslot[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int fx = e % FX, fy = e / FX;
+    sslot[k] = e < FX * FY ? e : -1;
+    const int gx = reflect_idx(ox - 2 * D + fx, nx);
+    const int gy = reflect_idx(oy - 2 * D + min(fy, FY - 1), ny);
+    soff[k] = gy * nx + gx;
+  }
+  const int lowoff = reflect_idx(px, nx) + nx * reflect_idx(py, ny);
+  float* const sflat0 = &sbuf[0][0][0];
+  float* const sflat1 = &sbuf[1][0][0];
 
-  for (int za = z_begin - D; za < z_end + D; ++za) {
-    stage(za + D);
+  for (int cls = 0; cls < D; ++cls) {
+    const int z0 = z_begin + cls;
+    if (z0 >= z_end) break;
+    const int z1 = z0 + ((z_end - 1 - z0) / D) * D;  // last output slice of the chain
+    // slices zs_i = z0 - 2d + i d, i = 0 .. last
+    const int last = (z1 - z0) / D + 4;
+    float nxt[NS];
+    auto load_slice = [&](int i) {
+      const size_t zoff = (size_t)reflect_idx(z0 - 2 * D + i * D, nz) * plane;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) nxt[k] = sslot[k] >= 0 ? ld(in + zoff + soff[k]) : 0.f;
+    };
+    auto store_slice = [&](int i) {
+      float* const dst = (i & 1) ? sflat1 : sflat0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (sslot[k] >= 0) dst[sslot[k]] = nxt[k];
+    };
+    float b0[9], b1[9], b2[9], c0[9], c1[9], c2[9];
+    // prologue: slices 0 and 1 give the xy bands of za - d and za for the
+    // first coefficient slice za = z0 - d
+    load_slice(0);
+    store_slice(0);
+    load_slice(1);
     __syncthreads();
-    // ---- analysis at (px, py, za): b_lm on the three slices za - d, za, za + d
-    float b[3][9];
-#pragma unroll
-    for (int sl = 0; sl < 3; ++sl) {
-      const int zs = za + (sl - 1) * D;  // sl = 0: za - d (f[n - d]), 2: za + d
-      const int slot = ((zs % M) + M) % M;
-      float a[3][3];  // a[row][l]: x-filtered rows y - d, y, y + d
-#pragma unroll
-      for (int ry = 0; ry < 3; ++ry) {
-        const int fy = ty + D + (ry - 1) * D;
-        const float fm = fring[slot][fy][tx], f0 = fring[slot][fy][tx + D],
-                    fp = fring[slot][fy][tx + 2 * D];
-        conv3(fm, f0, fp, a[ry][0], a[ry][1], a[ry][2]);
-      }
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        float o0, o1, o2;
-        conv3(a[0][l], a[1][l], a[2][l], o0, o1, o2);
-        b[sl][0 * 3 + l] = o0;  // index 3m + l
-        b[sl][1 * 3 + l] = o1;
-        b[sl][2 * 3 + l] = o2;
-      }
-    }
-    float alpha[27];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      float o0, o1, o2;
-      conv3(b[0][q], b[1][q], b[2][q], o0, o1, o2);
-      alpha[q] = o0;       // n = 0
-      alpha[9 + q] = o1;   // n = 1
-      alpha[18 + q] = o2;  // n = 2
-    }
-    // ---- shrink (Eq. (2))
-    float n2 = 0.f;
-#pragma unroll
-    for (int q = 1; q < 27; ++q) n2 = fmaf(alpha[q], alpha[q], n2);
-    const float nrm = sqrtf(n2);
-    const float sh = nrm <= lambda ? 0.f : 1.f - lambda / nrm;
-#pragma unroll
-    for (int q = 1; q < 27; ++q) alpha[q] *= sh;
-    if (HAS_LOW) {
-      const int gx = reflect_idx(px, nx), gy = reflect_idx(py, ny), gz = reflect_idx(za, nz);
-      alpha[0] = ld(low + ((size_t)gz * ny + gy) * nx + gx);
-    }
-    // ---- fold along z into the accumulators of output slices za+d, za, za-d
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const float a0 = alpha[q], a1 = alpha[9 + q], a2 = alpha[18 + q];
-      const float up = fmaf(0.25f, a0 - a2, kH1 * a1);    // to zo = za + d (tap m = -1)
-      const float mid = 0.5f * (a0 + a2);                 // to zo = za
-      const float dn = fmaf(0.25f, a0 - a2, -kH1 * a1);   // to zo = za - d (tap m = +1)
-      const int zu = za + D, zd = za - D;
-      if (zu >= z_begin && zu < z_end) cacc[zu % M][q][ty][tx] += up;
-      if (za >= z_begin && za < z_end) cacc[za % M][q][ty][tx] += mid;
-      if (zd >= z_begin && zd < z_end) cacc[zd % M][q][ty][tx] += dn;
-    }
+    xy_bands<D>(sbuf[0], tx, ty, b0);
+    store_slice(1);
+    load_slice(2);
     __syncthreads();
-    // ---- output slice zo = za - d is complete
-    const int zo = za - D;
-    if (zo >= z_begin && zo < z_end) {
-      const int slot = zo % M;
-      const bool interior = tx >= D && tx < HX - D && ty >= D && ty < HY - D;
-      if (interior && px < nx && py < ny) {
-        float v = 0.f;
+    xy_bands<D>(sbuf[1], tx, ty, b1);
+    store_slice(2);
+    if (last >= 3) load_slice(3);
+    __syncthreads();
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          float col[3];  // y-correlated sums at x - d, x, x + d
+    for (int q = 0; q < 9; ++q) c0[q] = c1[q] = 0.f;
+
+    // Step i (2 <= i <= last): slice i is staged in buffer i & 1 and slice
+    // i + 1 is in registers.  bo, bm = xy bands of za - d, za (za = zs_i - d);
+    // bn receives those of za + d.  cx, cy, cz = accumulators of za - d, za,
+    // za + d (cz is set here: za + d has no earlier contribution).  Returns
+    // true after the last step.
+    auto step = [&](int i, float (&bo)[9], float (&bm)[9], float (&bn)[9], float (&cx)[9],
+                    float (&cy)[9], float (&cz)[9]) -> bool {
+      const int za = z0 - D + (i - 2) * D;
+      xy_bands<D>(sbuf[i & 1], tx, ty, bn);
+      float low0 = 0.f;
+      if (HAS_LOW) low0 = ld(low + (size_t)reflect_idx(za, nz) * plane + lowoff);
+      // ---- analysis in z: alpha[9n + q] = h_n (z) b_q
+      float alpha[27];
 #pragma unroll
-          for (int cx = 0; cx < 3; ++cx) {
-            const int xx = tx + (cx - 1) * D;
-            float s = 0.f;
+      for (int q = 0; q < 9; ++q) conv3(bo[q], bm[q], bn[q], alpha[q], alpha[9 + q], alpha[18 + q]);
+      // ---- shrink (Eq. (2))
+      float n2 = 0.f;
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
-              s += corr3(m, cacc[slot][3 * m + l][ty - D][xx], cacc[slot][3 * m + l][ty][xx],
-                         cacc[slot][3 * m + l][ty + D][xx]);
-            col[cx] = s;
-          }
-          v += corr3(l, col[0], col[1], col[2]);
-        }
-        // H: negative voxels to zero; a NaN stays NaN (fmaxf would map it to 0
-        // and hide a failed reconstruction from the non-finite check)
-        if (positivity) v = v < 0.f ? 0.f : v;
-        const size_t o = ((size_t)zo * ny + py) * nx + px;
-        st(out + o, v);
-        if (MOM) {
-          const float fn = ld(out + o);
-          st(vnext + o, fmaf(mom, fn - ld(fcur + o), fn));
-        }
+      for (int q = 1; q < 27; ++q) n2 = fmaf(alpha[q], alpha[q], n2);
+      const float nrm = sqrtf(n2);
+      const float sh = nrm <= lambda ? 0.f : 1.f - lambda / nrm;
+#pragma unroll
+      for (int q = 1; q < 27; ++q) alpha[q] *= sh;
+      if (HAS_LOW) alpha[0] = low0;
+      // ---- fold along z into the accumulators of za + d, za, za - d
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float a0 = alpha[q], a1 = alpha[9 + q], a2 = alpha[18 + q];
+        cz[q] = fmaf(0.25f, a0 - a2, kH1 * a1);        // tap m = -1
+        cy[q] += 0.5f * (a0 + a2);                      // tap m = 0
+        cx[q] += fmaf(0.25f, a0 - a2, -kH1 * a1);       // tap m = +1
+      }
+      // ---- stage the next slice, and publish it and (below) slice za - d
+      const int zo = za - D;
+      const bool emit = i >= 4;
+      if (emit) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cbuf[q][ty][tx] = cx[q];
+      }
+      if (i < last) {
+        store_slice(i + 1);
+        if (i + 2 <= last) load_slice(i + 2);
       }
       __syncthreads();
+      if (emit) {
+        // y correlation of the 9 partial sums, for the rows the x
+        // correlation reads
+        if (ycorr) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) cacc[slot][q][ty][tx] = 0.f;
+          for (int l = 0; l < 3; ++l) {
+            float sy = 0.f;
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+              sy += corr3(m, cbuf[3 * m + l][ty - D][tx], cbuf[3 * m + l][ty][tx],
+                          cbuf[3 * m + l][ty + D][tx]);
+            colbuf[l][ty][tx] = sy;
+          }
+        }
+        __syncthreads();
+        if (writer) {
+          float v = 0.f;
+#pragma unroll
+          for (int l = 0; l < 3; ++l)
+            v += corr3(l, colbuf[l][ty][tx - D], colbuf[l][ty][tx], colbuf[l][ty][tx + D]);
+          // H: negative voxels to zero; a NaN stays NaN (fmaxf would map it to
+          // 0 and hide a failed reconstruction from the non-finite check)
+          if (positivity) v = v < 0.f ? 0.f : v;
+          const size_t o = (size_t)zo * plane + (size_t)py * nx + px;
+          st(out + o, v);
+          if (MOM) {
+            const float fn = ld(out + o);
+            st(vnext + o, fmaf(mom, fn - ld(fcur + o), fn));
+          }
+        }
+      }
+      return i >= last;
+    };
+    // the accumulator of za - d is complete after its step; its registers
+    // become the accumulator of za + 2d, which the next step sets
+    for (int i = 2;; i += 3) {
+      if (step(i, b0, b1, b2, c0, c1, c2)) break;
+      if (step(i + 1, b1, b2, b0, c1, c2, c0)) break;
+      if (step(i + 2, b2, b0, b1, c2, c0, c1)) break;
     }
+    __syncthreads();  // the next chain restages both buffers
   }
 }
 
