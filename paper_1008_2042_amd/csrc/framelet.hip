@@ -9,29 +9,45 @@
 // The coefficients computed from that extension at a position just outside
 // the grid equal (+-) the coefficients at the mirrored inside position, with
 // the sign of the band's filter symmetry, and the shrink factor is the same
-// there.  So running analysis + shrink on a halo of d voxels around the tile
-// (from reflected input) and then correlating with the filters gives exactly
-// the adjoint W^T of the reflected convolution, with no special edge code.
+// there.  So evaluating analysis + shrink on a halo of d voxels around the
+// tile (from reflected input) and synthesising from those positions gives
+// exactly the adjoint W^T of the reflected convolution, with no special edge
+// code.
+//
+// Evaluation.  The filter bank's 3 x 3 matrix H[l][m] = h_l[m] has
+// orthogonal columns: sum_l h_l[m] h_l[k] = c_m [m == k] with c = (1/4, 1/2,
+// 1/4), which is h0 itself.  Two exact consequences follow for the
+// tensor-product bank, with K the separable [1,2,1]/4 smoothing (taps -d, 0,
+// +d on every axis) and s(p) the shrink factor at coefficient position p:
+//   * sum over all 27 bands of W_b^T (s W_b f) = f K(s), so that
+//     W^T T W f = f K(s) + K(L - s alpha_0), where alpha_0 = K f is the low
+//     band and L the value T keeps for it (alpha_0 itself, or the coarser
+//     level's result with two levels);
+//   * sum over all 27 bands of (W_b f)(p)^2 = K(f^2)(p).
+// The kernel evaluates these forms, with the high-band energy of a position
+// written as sums of squares (no cancellation): per slice, the xy energy of
+// the 8 bands other than the xy low band is the weighted variance
+// E = sum_k w_k (f_k - b0)^2 over the 3 x 3 neighbourhood (w = [1,2,1]/4 in
+// x times in y, b0 = the xy low band), and
+//   ||alpha_high||^2 = (E(z - d) + 2 E(z) + E(z + d)) / 4 + a01^2 + a02^2
+// with a01, a02 the two z-high bands of b0.  The result equals the
+// 27-band analysis, shrink and synthesis up to rounding.
 //
 // Mapping: a block owns an HX x HY tile of (x, y) positions (one thread
 // each) = the output tile plus a halo of d, and marches along z over a chunk
 // of output slices, one chain per residue of z modulo d (with dilation d the
-// three slices a coefficient or an output reads are d apart, so the residue
-// classes never mix).  Per step of a chain (slice zs = za + d) a thread
-//   1. filters the staged slice zs in x and y at its position (9 LDS reads),
-//      giving the 9 xy bands b_lm of that slice;
-//   2. filters in z the b of slices za - d, za, za + d held in registers,
-//      giving the 27 coefficients at (x, y, za), and shrinks the 26 high bands
-//      by max(1 - lambda/||alpha_h||, 0);
-//   3. folds them along z into register accumulators c_lm of output slices
-//      za - d, za, za + d, after which slice za - d is complete;
-//   4. writes the next slice (loaded into registers at the start of the step)
-//      to the other LDS buffer, and, when za - d is an output slice,
-//      correlates its c_lm in y (27 LDS reads) and then in x (9 reads) for the
-//      interior positions and writes the voxel, with H and the momentum
-//      epilogue.
-// b and c rotate through three register sets (the loop is unrolled three
-// times), so nothing moves between registers; a step costs two barriers.
+// slices a coefficient or an output reads are d apart, so the residue
+// classes never mix).  Per step of a chain (staged slice zs) a thread
+//   1. reads the 3 x 3 neighbourhood of its position in slice zs from LDS and
+//      forms b0 and E there;
+//   2. from b0 and E of slices za - d, za, za + d (za = zs - d, held in
+//      registers) forms the shrink factor s and R = L - s alpha_0 at za;
+//   3. smooths s and R in z over za - 2d, za - d, za and writes the two sums
+//      for slice zo = za - d to LDS, and stages the next slice;
+//   4. after the step's one barrier, smooths the two in x and y and writes
+//      f K(s) + K(R) at (x, y, zo), with H and the momentum epilogue.
+// The staged slices and the smoothed pairs are double-buffered in LDS, so a
+// step needs one barrier.
 #include "tfcb_internal.h"
 
 namespace tfcb {
@@ -45,41 +61,10 @@ __device__ __forceinline__ int reflect_idx(int j, int n) {
   return j;
 }
 
-// Convolution of a triple (f[n-d], f[n], f[n+d]) with h0, h1, h2.
-// (A_l f)[n] = sum_m h_l[m] f[n - m d], h listed as h[-1], h[0], h[+1].
-__device__ __forceinline__ void conv3(float fm, float f0, float fp, float& o0, float& o1,
-                                      float& o2) {
-  const float s = fp + fm;
-  o0 = fmaf(0.25f, s, 0.5f * f0);
-  o1 = kH1 * (fp - fm);
-  o2 = fmaf(-0.25f, s, 0.5f * f0);
-}
-
-// Correlation sum_m h_l[m] c[n + m d] for one filter l, values at n-d, n, n+d.
-__device__ __forceinline__ float corr3(int l, float cm, float c0, float cp) {
-  if (l == 0) return fmaf(0.25f, cm + cp, 0.5f * c0);
-  if (l == 1) return kH1 * (cm - cp);
-  return fmaf(-0.25f, cm + cp, 0.5f * c0);
-}
-
 }  // namespace
 
-// The xy bands of one staged slice at (tx, ty): x filter of rows y - d, y,
-// y + d, then y filter; b[3m + l] = h_m (y) h_l (x).
-template <int D, int FX, int FY>
-__device__ __forceinline__ void xy_bands(const float (&sl)[FY][FX], int tx, int ty, float (&b)[9]) {
-  float a[3][3];  // a[row][l]: x-filtered rows y - d, y, y + d
-#pragma unroll
-  for (int ry = 0; ry < 3; ++ry) {
-    const int fy = ty + D + (ry - 1) * D;
-    conv3(sl[fy][tx], sl[fy][tx + D], sl[fy][tx + 2 * D], a[ry][0], a[ry][1], a[ry][2]);
-  }
-#pragma unroll
-  for (int l = 0; l < 3; ++l) conv3(a[0][l], a[1][l], a[2][l], b[l], b[3 + l], b[6 + l]);
-}
-
 template <typename T, int D, int HX, int HY, bool HAS_LOW, bool MOM>
-__global__ __launch_bounds__(HX* HY, HAS_LOW ? 3 : 4) void k_framelet(int nx, int ny, int nz, int zchunk,
+__global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int zchunk,
                                                       float lambda, int positivity,
                                                       const T* __restrict__ in,
                                                       const T* __restrict__ low,
@@ -90,8 +75,7 @@ __global__ __launch_bounds__(HX* HY, HAS_LOW ? 3 : 4) void k_framelet(int nx, in
   constexpr int NT = HX * HY;
   constexpr int NS = (FX * FY + NT - 1) / NT;  // staged elements per thread
   __shared__ float sbuf[2][FY][FX];
-  __shared__ float cbuf[9][HY][HX];
-  __shared__ float colbuf[3][HY][HX];
+  __shared__ float kbuf[2][2][HY][HX];  // z-smoothed s and R, per step parity
 
   const int tx = threadIdx.x % HX, ty = threadIdx.x / HX;
   const int ox = blockIdx.x * (HX - 2 * D);  // first output x of the tile
@@ -100,9 +84,7 @@ __global__ __launch_bounds__(HX* HY, HAS_LOW ? 3 : 4) void k_framelet(int nx, in
   const int z_end = min(nz, z_begin + zchunk);
   // this thread's position (may be a halo position outside the grid)
   const int px = ox + tx - D, py = oy + ty - D;
-  const bool interior = tx >= D && tx < HX - D && ty >= D && ty < HY - D;
-  const bool ycorr = ty >= D && ty < HY - D;
-  const bool writer = interior && px < nx && py < ny;
+  const bool writer = tx >= D && tx < HX - D && ty >= D && ty < HY - D && px < nx && py < ny;
   const size_t plane = (size_t)nx * ny;
 
   // staged elements of this thread: in-plane offsets (reflected) and LDS slots
@@ -124,7 +106,7 @@ __global__ __launch_bounds__(HX* HY, HAS_LOW ? 3 : 4) void k_framelet(int nx, in
     const int z0 = z_begin + cls;
     if (z0 >= z_end) break;
     const int z1 = z0 + ((z_end - 1 - z0) / D) * D;  // last output slice of the chain
-    // slices zs_i = z0 - 2d + i d, i = 0 .. last
+    // staged slices zs_i = z0 - 2d + i d, i = 0 .. last
     const int last = (z1 - z0) / D + 4;
     float nxt[NS];
     auto load_slice = [&](int i) {
@@ -138,140 +120,154 @@ __global__ __launch_bounds__(HX* HY, HAS_LOW ? 3 : 4) void k_framelet(int nx, in
       for (int k = 0; k < NS; ++k)
         if (sslot[k] >= 0) dst[sslot[k]] = nxt[k];
     };
-    float b0[9], b1[9], b2[9], c0[9], c1[9], c2[9];
-    // prologue: slices 0 and 1 give the xy bands of za - d and za for the
-    // first coefficient slice za = z0 - d
     load_slice(0);
     store_slice(0);
     load_slice(1);
     __syncthreads();
-    xy_bands<D>(sbuf[0], tx, ty, b0);
-    store_slice(1);
-    load_slice(2);
-    __syncthreads();
-    xy_bands<D>(sbuf[1], tx, ty, b1);
-    store_slice(2);
-    if (last >= 3) load_slice(3);
-    __syncthreads();
+    // rolling values, oldest first: b0 and E of slices zs - 2d, zs - d, zs;
+    // f at this position for zs - 2d, zs - d, zs; s and R of za - 2d, za - d, za
+    float b0o = 0.f, b0m = 0.f, b0n = 0.f, eo = 0.f, em = 0.f, en = 0.f;
+    float fco = 0.f, fcm = 0.f, fcn = 0.f;
+    float sho = 0.f, shm = 0.f, shn = 0.f, ro = 0.f, rm = 0.f, rn = 0.f;
+    for (int i = 0; i <= last; ++i) {
+      const int zs = z0 - 2 * D + i * D;
+      const int za = zs - D, zo = za - D;
+      float lowv = 0.f;
+      if (HAS_LOW && i >= 2) lowv = ld(low + (size_t)reflect_idx(za, nz) * plane + lowoff);
+      // ---- 1. xy low band and xy high-band energy of slice zs
+      {
+        const float (&sl)[FY][FX] = sbuf[i & 1];
+        float f[3][3];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) c0[q] = c1[q] = 0.f;
-
-    // Step i (2 <= i <= last): slice i is staged in buffer i & 1 and slice
-    // i + 1 is in registers.  bo, bm = xy bands of za - d, za (za = zs_i - d);
-    // bn receives those of za + d.  cx, cy, cz = accumulators of za - d, za,
-    // za + d (cz is set here: za + d has no earlier contribution).  Returns
-    // true after the last step.
-    auto step = [&](int i, float (&bo)[9], float (&bm)[9], float (&bn)[9], float (&cx)[9],
-                    float (&cy)[9], float (&cz)[9]) -> bool {
-      const int za = z0 - D + (i - 2) * D;
-      xy_bands<D>(sbuf[i & 1], tx, ty, bn);
-      float low0 = 0.f;
-      if (HAS_LOW) low0 = ld(low + (size_t)reflect_idx(za, nz) * plane + lowoff);
-      // ---- analysis in z: alpha[9n + q] = h_n (z) b_q
-      float alpha[27];
+        for (int ry = 0; ry < 3; ++ry)
 #pragma unroll
-      for (int q = 0; q < 9; ++q) conv3(bo[q], bm[q], bn[q], alpha[q], alpha[9 + q], alpha[18 + q]);
-      // ---- shrink (Eq. (2))
-      float n2 = 0.f;
+          for (int rx = 0; rx < 3; ++rx) f[ry][rx] = sl[ty + ry * D][tx + rx * D];
+        float r[3];
 #pragma unroll
-      for (int q = 1; q < 27; ++q) n2 = fmaf(alpha[q], alpha[q], n2);
-      const float nrm = sqrtf(n2);
-      const float sh = nrm <= lambda ? 0.f : 1.f - lambda / nrm;
+        for (int ry = 0; ry < 3; ++ry) r[ry] = fmaf(0.25f, f[ry][0] + f[ry][2], 0.5f * f[ry][1]);
+        const float b0 = fmaf(0.25f, r[0] + r[2], 0.5f * r[1]);
+        float dv[3][3];
 #pragma unroll
-      for (int q = 1; q < 27; ++q) alpha[q] *= sh;
-      if (HAS_LOW) alpha[0] = low0;
-      // ---- fold along z into the accumulators of za + d, za, za - d
+        for (int ry = 0; ry < 3; ++ry)
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const float a0 = alpha[q], a1 = alpha[9 + q], a2 = alpha[18 + q];
-        cz[q] = fmaf(0.25f, a0 - a2, kH1 * a1);        // tap m = -1
-        cy[q] += 0.5f * (a0 + a2);                      // tap m = 0
-        cx[q] += fmaf(0.25f, a0 - a2, -kH1 * a1);       // tap m = +1
+          for (int rx = 0; rx < 3; ++rx) dv[ry][rx] = f[ry][rx] - b0;
+        const float corner = fmaf(dv[0][0], dv[0][0], fmaf(dv[0][2], dv[0][2],
+                             fmaf(dv[2][0], dv[2][0], dv[2][2] * dv[2][2])));
+        const float edge = fmaf(dv[0][1], dv[0][1], fmaf(dv[1][0], dv[1][0],
+                           fmaf(dv[1][2], dv[1][2], dv[2][1] * dv[2][1])));
+        const float e = fmaf(0.0625f, corner, fmaf(0.125f, edge, 0.25f * (dv[1][1] * dv[1][1])));
+        b0o = b0m; b0m = b0n; b0n = b0;
+        eo = em; em = en; en = e;
+        fco = fcm; fcm = fcn; fcn = f[1][1];
       }
-      // ---- stage the next slice, and publish it and (below) slice za - d
-      const int zo = za - D;
+      // ---- 2. shrink factor and low-band remainder at za
+      if (i >= 2) {
+        const float a00 = fmaf(0.25f, b0o + b0n, 0.5f * b0m);
+        const float a01 = kH1 * (b0n - b0o);
+        const float a02 = fmaf(-0.25f, b0o + b0n, 0.5f * b0m);
+        const float n2 = fmaf(0.25f, eo + en, fmaf(0.5f, em, fmaf(a01, a01, a02 * a02)));
+        const float nrm = sqrtf(n2);
+        const float sh = nrm <= lambda ? 0.f : 1.f - lambda / nrm;
+        const float L = HAS_LOW ? lowv : a00;
+        sho = shm; shm = shn; shn = sh;
+        ro = rm; rm = rn; rn = fmaf(-sh, a00, L);
+      }
+      // ---- 3. z sums for slice zo, and the next slice into the other buffer
       const bool emit = i >= 4;
       if (emit) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) cbuf[q][ty][tx] = cx[q];
+        kbuf[i & 1][0][ty][tx] = fmaf(0.25f, sho + shn, 0.5f * shm);
+        kbuf[i & 1][1][ty][tx] = fmaf(0.25f, ro + rn, 0.5f * rm);
       }
       if (i < last) {
         store_slice(i + 1);
         if (i + 2 <= last) load_slice(i + 2);
       }
       __syncthreads();
-      if (emit) {
-        // y correlation of the 9 partial sums, for the rows the x
-        // correlation reads
-        if (ycorr) {
+      // ---- 4. xy sums and the output voxel
+      if (emit && writer) {
+        float ks[2];
 #pragma unroll
-          for (int l = 0; l < 3; ++l) {
-            float sy = 0.f;
+        for (int w = 0; w < 2; ++w) {
+          float r[3];
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
-              sy += corr3(m, cbuf[3 * m + l][ty - D][tx], cbuf[3 * m + l][ty][tx],
-                          cbuf[3 * m + l][ty + D][tx]);
-            colbuf[l][ty][tx] = sy;
+          for (int ry = 0; ry < 3; ++ry) {
+            const float* row = &kbuf[i & 1][w][ty + (ry - 1) * D][tx];
+            r[ry] = fmaf(0.25f, row[-D] + row[D], 0.5f * row[0]);
           }
+          ks[w] = fmaf(0.25f, r[0] + r[2], 0.5f * r[1]);
         }
-        __syncthreads();
-        if (writer) {
-          float v = 0.f;
-#pragma unroll
-          for (int l = 0; l < 3; ++l)
-            v += corr3(l, colbuf[l][ty][tx - D], colbuf[l][ty][tx], colbuf[l][ty][tx + D]);
-          // H: negative voxels to zero; a NaN stays NaN (fmaxf would map it to
-          // 0 and hide a failed reconstruction from the non-finite check)
-          if (positivity) v = v < 0.f ? 0.f : v;
-          const size_t o = (size_t)zo * plane + (size_t)py * nx + px;
-          st(out + o, v);
-          if (MOM) {
-            const float fn = ld(out + o);
-            st(vnext + o, fmaf(mom, fn - ld(fcur + o), fn));
-          }
+        float v = fmaf(fco, ks[0], ks[1]);
+        // H: negative voxels to zero; a NaN stays NaN (fmaxf would map it to
+        // 0 and hide a failed reconstruction from the non-finite check)
+        if (positivity) v = v < 0.f ? 0.f : v;
+        const size_t o = (size_t)zo * plane + (size_t)py * nx + px;
+        st(out + o, v);
+        if (MOM) {
+          const float fn = ld(out + o);
+          st(vnext + o, fmaf(mom, fn - ld(fcur + o), fn));
         }
       }
-      return i >= last;
-    };
-    // the accumulator of za - d is complete after its step; its registers
-    // become the accumulator of za + 2d, which the next step sets
-    for (int i = 2;; i += 3) {
-      if (step(i, b0, b1, b2, c0, c1, c2)) break;
-      if (step(i + 1, b1, b2, b0, c1, c2, c0)) break;
-      if (step(i + 2, b2, b0, b1, c2, c0, c1)) break;
     }
     __syncthreads();  // the next chain restages both buffers
   }
+}
+
+// Blocks resident per CU for a kernel, and the CU count, cached per kernel.
+template <typename K>
+static int resident_slots(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return 1024;
+  return max(1, cus * per_cu);
+}
+
+template <typename T, int D, int HX, int HY, bool HAS_LOW, bool MOM>
+static hipError_t launch_fw1(int nx, int ny, int nz, float lambda, int positivity, const T* in,
+                             const T* low, T* out, const T* fcur, T* vnext, float mom,
+                             hipStream_t s) {
+  auto kern = k_framelet<T, D, HX, HY, HAS_LOW, MOM>;
+  static const int slots = resident_slots(kern, HX * HY);
+  const int tox = HX - 2 * D, toy = HY - 2 * D;
+  const long gx = (nx + tox - 1) / tox, gy = (ny + toy - 1) / toy;
+  // Split z into chunks: a chunk costs its slices plus 4 d steps of halo, and
+  // the launch takes ceil(blocks / resident slots) rounds; pick the split
+  // with the least rounds x steps (the fewest chunks on a tie).
+  int zchunk = nz;
+  long best = -1;
+  for (int chunks = 1; chunks <= nz; ++chunks) {
+    const int zc = (nz + chunks - 1) / chunks;
+    if (chunks > 1 && zc < 4 * D) break;
+    const long nb = gx * gy * ((nz + zc - 1) / zc);
+    const long cost = ((nb + slots - 1) / slots) * (long)(zc + 4 * D);
+    if (best < 0 || cost < best) {
+      best = cost;
+      zchunk = zc;
+    }
+  }
+  dim3 grid((unsigned)gx, (unsigned)gy, (nz + zchunk - 1) / zchunk);
+  hipLaunchKernelGGL(kern, grid, dim3(HX * HY), 0, s, nx, ny, nz, zchunk, lambda, positivity, in,
+                     low, out, fcur, vnext, mom);
+  return hipGetLastError();
 }
 
 template <typename T, int D, int HX, int HY>
 static hipError_t launch_fw(int nx, int ny, int nz, float lambda, int positivity, const T* in,
                             const T* low, T* out, const T* fcur, T* vnext, float mom,
                             hipStream_t s) {
-  const int tox = HX - 2 * D, toy = HY - 2 * D;
-  const int gx = (nx + tox - 1) / tox, gy = (ny + toy - 1) / toy;
-  // split z so the launch has enough blocks to fill the chip
-  int chunks = 1;
-  while ((long)gx * gy * chunks < 1024 && nz / (chunks * 2) >= 8 * D) chunks *= 2;
-  const int zchunk = (nz + chunks - 1) / chunks;
-  dim3 grid(gx, gy, (nz + zchunk - 1) / zchunk);
-  dim3 block(HX * HY);
   if (low) {
     if (vnext)
-      hipLaunchKernelGGL((k_framelet<T, D, HX, HY, true, true>), grid, block, 0, s, nx, ny, nz,
-                         zchunk, lambda, positivity, in, low, out, fcur, vnext, mom);
-    else
-      hipLaunchKernelGGL((k_framelet<T, D, HX, HY, true, false>), grid, block, 0, s, nx, ny, nz,
-                         zchunk, lambda, positivity, in, low, out, fcur, vnext, mom);
-  } else {
-    if (vnext)
-      hipLaunchKernelGGL((k_framelet<T, D, HX, HY, false, true>), grid, block, 0, s, nx, ny, nz,
-                         zchunk, lambda, positivity, in, low, out, fcur, vnext, mom);
-    else
-      hipLaunchKernelGGL((k_framelet<T, D, HX, HY, false, false>), grid, block, 0, s, nx, ny, nz,
-                         zchunk, lambda, positivity, in, low, out, fcur, vnext, mom);
+      return launch_fw1<T, D, HX, HY, true, true>(nx, ny, nz, lambda, positivity, in, low, out,
+                                                  fcur, vnext, mom, s);
+    return launch_fw1<T, D, HX, HY, true, false>(nx, ny, nz, lambda, positivity, in, low, out,
+                                                 fcur, vnext, mom, s);
   }
-  return hipGetLastError();
+  if (vnext)
+    return launch_fw1<T, D, HX, HY, false, true>(nx, ny, nz, lambda, positivity, in, low, out,
+                                                 fcur, vnext, mom, s);
+  return launch_fw1<T, D, HX, HY, false, false>(nx, ny, nz, lambda, positivity, in, low, out,
+                                                fcur, vnext, mom, s);
 }
 
 template <typename T>
@@ -281,9 +277,8 @@ hipError_t launch_framelet(int nx, int ny, int nz, int dil, float lambda, int po
   if (dil == 1)
     return launch_fw<T, 1, 32, 16>(nx, ny, nz, lambda, positivity, in, low, out, fcur, vnext, mom,
                                    s);
-  // dilation 2 keeps five slices in flight: a 32 x 8 tile keeps LDS at 55 KB
-  return launch_fw<T, 2, 32, 8>(nx, ny, nz, lambda, positivity, in, low, out, fcur, vnext, mom,
-                                s);
+  return launch_fw<T, 2, 32, 16>(nx, ny, nz, lambda, positivity, in, low, out, fcur, vnext, mom,
+                                 s);
 }
 
 // low = A0^3 in: the level-1 low band (h0 in x, y, z; reflected edges).
