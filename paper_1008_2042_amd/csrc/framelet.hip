@@ -86,6 +86,7 @@ __global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int
   const int px = ox + tx - D, py = oy + ty - D;
   const bool writer = tx >= D && tx < HX - D && ty >= D && ty < HY - D && px < nx && py < ny;
   const size_t plane = (size_t)nx * ny;
+  const float lam2 = lambda * lambda;
 
   // staged elements of this thread: in-plane offsets (reflected) and LDS slots
   int soff[NS], sslot[NS];
@@ -166,8 +167,10 @@ __global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int
         const float a01 = kH1 * (b0n - b0o);
         const float a02 = fmaf(-0.25f, b0o + b0n, 0.5f * b0m);
         const float n2 = fmaf(0.25f, eo + en, fmaf(0.5f, em, fmaf(a01, a01, a02 * a02)));
-        const float nrm = sqrtf(n2);
-        const float sh = nrm <= lambda ? 0.f : 1.f - lambda / nrm;
+        // s = max(1 - lambda / ||alpha_h||, 0), with the hardware reciprocal
+        // square root (1 ulp); the clamp keeps it finite for lambda = 0
+        const float sh = n2 <= lam2 ? 0.f
+                                    : 1.f - lambda * __builtin_amdgcn_rsqf(fmaxf(n2, 1e-30f));
         const float L = HAS_LOW ? lowv : a00;
         sho = shm; shm = shn; shn = sh;
         ro = rm; rm = rn; rn = fmaf(-sh, a00, L);
