@@ -124,7 +124,7 @@ struct CglsScalars {
   int32_t breakdowns;  // number of CGLS calls stopped so far
 };
 
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 1024;
 
 // Deterministic block sum of one FP64 value per thread (blockDim a multiple
 // of 64): wavefront butterfly, then the wave sums in order by thread 0.

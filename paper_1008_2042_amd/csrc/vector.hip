@@ -12,9 +12,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_finalize(const double* __res
                                                              CglsScalars* __restrict__ sc,
                                                              double nvox) {
   __shared__ double red[kReduceThreads / 64];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kReduceThreads) v += partials[i];
-  const double sum = wave_block_sum(v, red);
+  // four independent partial sums per thread keep four loads in flight; the
+  // order is fixed, so the result is the same on every call
+  constexpr int T = kReduceThreads;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * T < n; i += 4 * T) {
+    v0 += partials[i];
+    v1 += partials[i + T];
+    v2 += partials[i + 2 * T];
+    v3 += partials[i + 3 * T];
+  }
+  for (; i < n; i += T) v0 += partials[i];
+  const double sum = wave_block_sum((v0 + v1) + (v2 + v3), red);
   if (threadIdx.x != 0) return;
   const double tiny = 1e-300;
   switch (mode) {
