@@ -1,7 +1,8 @@
 """The large single-reconstruction workload (512x512x256 at 0.5 mm, 360 views
 of a 1024x768 detector at 0.388 mm) at its real shape: sampled projector
 outputs against the oracle, the adjoint identity of the full-size operators,
-and a shortened 3-grid, 2-level-framelet reconstruction."""
+sampled framelet outputs at one and two levels, and a shortened 3-grid,
+2-level-framelet reconstruction."""
 import sys
 
 import numpy as np
@@ -50,6 +51,30 @@ def test_large_project_sampled_and_adjoint():
     lhs = float(torch.sum(pf.double() * y.double()))
     rhs = float(torch.sum(fd.double() * pty.double()))
     assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_large_framelet_sampled(levels):
+    """The fused framelet shrink at 512x512x256 (several z chunks per column
+    of blocks, and with two levels the dilation-2 chains of both z residues)
+    at sampled voxels, faces and corners included, against the oracle."""
+    dev = _dev()
+    g = LARGE["geom"]
+    f = inputs.random_volume(g, 44)
+    lam = 2e-3
+    announce("large framelet levels=%d" % levels)
+    got = tfcb.framelet_shrink(torch.tensor(f, dtype=torch.float32, device=dev), lam, levels,
+                               True).double().cpu().numpy()
+    rng = np.random.default_rng(45)
+    kji = np.stack([rng.integers(0, g.nz, 48), rng.integers(0, g.ny, 48),
+                    rng.integers(0, g.nx, 48)], axis=1)
+    edges = np.array([[0, 0, 0], [g.nz - 1, g.ny - 1, g.nx - 1], [0, g.ny // 2, g.nx - 1],
+                      [g.nz - 1, 0, g.nx // 3], [1, 1, 1], [g.nz - 2, g.ny - 2, 5],
+                      [g.nz // 2, 0, 0], [g.nz // 2 + 1, g.ny - 1, g.nx - 2]])
+    kji = np.concatenate([kji, edges])
+    want = oracle.framelet_shrink_voxels(f, lam, kji, levels, True)
+    a = got[kji[:, 0], kji[:, 1], kji[:, 2]]
+    assert np.linalg.norm(a - want) <= 1e-5 * np.linalg.norm(want)
 
 
 @pytest.mark.parametrize("storage", [tfcb.F32, tfcb.F16])
