@@ -206,7 +206,7 @@ __global__ __launch_bounds__(HX* HY) void k_framelet(int nx, int ny, int nz, int
         const size_t o = (size_t)zo * plane + (size_t)py * nx + px;
         st(out + o, v);
         if (MOM) {
-          const float fn = ld(out + o);
+          const float fn = as_stored<T>(v);
           st(vnext + o, fmaf(mom, fn - ld(fcur + o), fn));
         }
       }

@@ -193,12 +193,13 @@ __global__ __launch_bounds__(256) void k_project_siddon(GeomDev g, const ViewInf
     if (MODE == 0) {
       st(out + o, sum);
     } else if (MODE == 1) {
-      st(out + o, ld(gin + o) - sum);
-      const float rs = ld(out + o);  // the stored (rounded) residual
+      const float res = ld(gin + o) - sum;
+      st(out + o, res);
+      const float rs = as_stored<T>(res);  // the stored (rounded) residual
       part = (double)rs * (double)rs;
     } else {
       st(out + o, sum);
-      const float qs = ld(out + o);
+      const float qs = as_stored<T>(sum);
       part = (double)qs * (double)qs;
     }
   }

@@ -199,12 +199,12 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
       } else if (MODE == 1) {
         const float res = ld(gin + o) - val;
         st(out + o, res);
-        const float rs = ld(out + o);  // the stored (rounded) residual
+        const float rs = as_stored<T>(res);  // the stored (rounded) residual
         st(rl + o, ell * rs);
         part += (double)rs * (double)rs;
       } else {
         st(out + o, val);
-        const float qs = ld(out + o);
+        const float qs = as_stored<T>(val);
         part += (double)qs * (double)qs;
       }
     }
@@ -500,12 +500,12 @@ __global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev
       } else if (MODE == 1) {
         const float res = ld(gin + o) - val;
         st(out + o, res);
-        const float rs = ld(out + o);  // the stored (rounded) residual
+        const float rs = as_stored<T>(res);  // the stored (rounded) residual
         st(rl + o, ell * rs);
         part += (double)rs * (double)rs;
       } else {
         st(out + o, val);
-        const float qs = ld(out + o);
+        const float qs = as_stored<T>(val);
         part += (double)qs * (double)qs;
       }
     }
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void k_residual_update(GeomDev g,
     if (!sc->stopped) {
       rv = rv - (float)sc->alpha * ld(q + o);
       st(r + o, rv);
-      rv = ld(r + o);
+      rv = as_stored<T>(rv);
     }
     st(rl + o, ray_length(g, vi, ci, row) * rv);
     part = (double)rv * (double)rv;

@@ -28,6 +28,17 @@ template <> __device__ __forceinline__ void st<__hip_bfloat16>(__hip_bfloat16* p
   *p = __float2bfloat16(v);
 }
 
+// st then ld of the same element, without the memory round trip: the value
+// as stored (rounded to nearest even for FP16 and BF16)
+template <typename T> __device__ __forceinline__ float as_stored(float v);
+template <> __device__ __forceinline__ float as_stored<float>(float v) { return v; }
+template <> __device__ __forceinline__ float as_stored<__half>(float v) {
+  return __half2float(__float2half(v));
+}
+template <> __device__ __forceinline__ float as_stored<__hip_bfloat16>(float v) {
+  return __bfloat162float(__float2bfloat16(v));
+}
+
 inline size_t dtype_size(tfcb_dtype dt) { return dt == TFCB_F32 ? 4 : 2; }
 
 // ------------------------------------------------------- padded copies
