@@ -88,7 +88,7 @@ def percentiles(lat: np.ndarray) -> Dict[str, float]:
 
 
 def serving_benchmark(n: int = 64, seed: int = 404, load: float = 0.8,
-                      arena_gb: float = 8.0, max_slots: int = 8, device=None,
+                      arena_gb: float = 8.0, max_slots: int = 3, device=None,
                       storage: int = tfcb.F16) -> Dict:
     import torch
     device = device or torch.device("cuda:0")
