@@ -633,6 +633,8 @@ hipError_t launch_prescale(const GeomDev& g, const ColInfo* cols, const ViewInfo
 }
 
 // r -= alpha q (skipped after a breakdown); rl = l * r; partial ||r||^2.
+constexpr int kResRows = 4;  // row groups per block of the residual update
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual_update(GeomDev g,
                                                          const ViewInfo* __restrict__ views,
@@ -643,21 +645,29 @@ __global__ __launch_bounds__(256) void k_residual_update(GeomDev g,
                                                          double* __restrict__ partials) {
   __shared__ double red[4];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int row = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int view = blockIdx.z;
   double part = 0.0;
-  if (c < g.nu && row < g.nv) {
+  if (c < g.nu) {
+    // a wave takes one row of 64 columns, the block kResRows groups of 4 rows
     const ViewInfo vi = views[view];
     const ColInfo ci = cols[(size_t)view * g.nu + c];
-    const size_t o = ((size_t)view * g.nv + row) * g.nu + c;
-    float rv = ld(r + o);
-    if (!sc->stopped) {
-      rv = rv - (float)sc->alpha * ld(q + o);
-      st(r + o, rv);
-      rv = as_stored<T>(rv);
+    const bool stopped = sc->stopped != 0;
+    const float alpha = (float)sc->alpha;
+#pragma unroll
+    for (int k = 0; k < kResRows; ++k) {
+      const int row = blockIdx.y * 4 * kResRows + 4 * k + (threadIdx.x >> 6);
+      if (row < g.nv) {
+        const size_t o = ((size_t)view * g.nv + row) * g.nu + c;
+        float rv = ld(r + o);
+        if (!stopped) {
+          rv = rv - alpha * ld(q + o);
+          st(r + o, rv);
+          rv = as_stored<T>(rv);
+        }
+        st(rl + o, ray_length(g, vi, ci, row) * rv);
+        part += (double)rv * (double)rv;
+      }
     }
-    st(rl + o, ray_length(g, vi, ci, row) * rv);
-    part = (double)rv * (double)rv;
   }
   const double s = wave_block_sum(part, red);
   if (threadIdx.x == 0)
@@ -669,7 +679,7 @@ hipError_t launch_residual_update(const GeomDev& g, const ViewInfo* views, const
                                   T* r, const T* q, T* rl, const CglsScalars* sc,
                                   double* partials, int* n_partials, hipStream_t s) {
   dim3 block(256);
-  dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_views);
+  dim3 grid((g.nu + 63) / 64, (g.nv + 4 * kResRows - 1) / (4 * kResRows), g.n_views);
   if (n_partials) *n_partials = (int)(grid.x * grid.y * grid.z);
   hipLaunchKernelGGL((k_residual_update<T>), grid, block, 0, s, g, views, cols, r, q, rl, sc,
                      partials);
