@@ -96,29 +96,94 @@ def load_traffic(kernel_idx: int):
     return ent.get("bytes_per_launch")
 
 
+def _host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _timed(fn, reps=1):
+    """Median wall time of reps calls after one untimed warm-up call when
+    reps > 1 (a single call is timed cold)."""
+    if reps > 1:
+        fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(sorted(ts)[len(ts) // 2])
+
+
 def cpu_baseline(cfg, y):
-    """The FP64 oracle on a bounded sample of the same workload: one outer
-    TF iteration (3 CGLS steps + framelet shrink) on the workload's coarse
-    grid (256x256x35 volume, 40 views of 256x192 binned data), timed on this
-    host's cores.  The full schedule's rate is extrapolated with the
-    fine/coarse work ratio 8 (rays x4, planes x2, voxels x8)."""
+    """The FP64 oracle, as it stands, on this host's cores.
+
+    Measured on the paper-scale workload: one outer TF iteration (3 CGLS
+    steps + framelet shrink) on its coarse grid (256x256x35, 40 views of
+    256x192 binned data) and one on its fine grid (512x512x70, 40 x 512x384);
+    the reconstruction time is 16 x coarse + 24 x fine from those two
+    measured numbers (the prolongation and restriction are negligible).
+    Also single applications of P, P^T and the framelet shrink on the fine
+    grid, and on the 64x64x16 tiny workload the same operators (median of 3)
+    and its whole 10-iteration reconstruction."""
     import numpy as np
     import oracle
+    from paper_1008_2042_amd import inputs
     g = cfg["geom"]
+    lam, n = cfg["lam"], cfg["cgls_steps"]
     gc = oracle.coarse_geom(g, True)
     yc = oracle.restrict_sino(g, y)
-    f0 = np.zeros((gc.nz, gc.ny, gc.nx))
-    t0 = time.perf_counter()
-    oracle.tf_iterations(gc, yc, f0, 1, cfg["lam"], cfg["cgls_steps"])
-    t_c = time.perf_counter() - t0
+    t_c = _timed(lambda: oracle.tf_iterations(gc, yc, np.zeros((gc.nz, gc.ny, gc.nx)), 1, lam, n))
+    t_f = _timed(lambda: oracle.tf_iterations(g, y, np.zeros(g.vol_shape), 1, lam, n))
+    f = inputs.random_volume(g, 1)
+    ops = {"P_s": _timed(lambda: oracle.project(g, f)),
+           "PT_s": _timed(lambda: oracle.backproject(g, y)),
+           "framelet_s": _timed(lambda: oracle.framelet_shrink(f, lam))}
+    tiny = inputs.config("tiny")
+    gt = tiny["geom"]
+    yt = inputs.measured_data(tiny)
+    ft = inputs.random_volume(gt, 2)
+    tiny_ops = {"P_s": _timed(lambda: oracle.project(gt, ft), 3),
+                "PT_s": _timed(lambda: oracle.backproject(gt, yt), 3),
+                "framelet_s": _timed(lambda: oracle.framelet_shrink(ft, lam), 3),
+                "recon_s": _timed(lambda: oracle.reconstruct(gt, yt, lam, tiny["iters"]), 3)}
     n_c, n_f = cfg["iters"]
-    recon_s = (n_c + 8.0 * n_f) * t_c
+    recon_s = n_c * t_c + n_f * t_f
     return {"value": round((n_c + n_f) / recon_s, 6), "unit": "TF iterations/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "1 outer TF iteration (3 CGLS steps + framelet shrink) of the coarse "
-                      "256x256x35 grid of this workload took %.2f s; full 16+24 schedule "
-                      "extrapolated as (16 + 8*24) x that = %.0f s per reconstruction"
-                      % (t_c, recon_s)}
+            "sample": "one outer TF iteration of each grid of this workload, measured: coarse "
+                      "256x256x35 %.2f s, fine 512x512x70 %.2f s; the 16+24 schedule is "
+                      "16 x %.2f + 24 x %.2f = %.0f s per reconstruction"
+                      % (t_c, t_f, t_c, t_f, recon_s),
+            "s_per_recon": round(recon_s, 1),
+            "coarse_iteration_s": round(t_c, 3), "fine_iteration_s": round(t_f, 3),
+            "operators_512x512x70_s": {k: round(v, 3) for k, v in ops.items()},
+            "tiny_64x64x16_s": {k: round(v, 4) for k, v in tiny_ops.items()},
+            "host": {"cpu_model": _host_cpu_model(), "nproc": os.cpu_count(),
+                     "omp_threads": oracle.num_threads()}}
+
+
+def oracle_samples_error(vol):
+    """Relative L2 error of a paper-scale GPU volume against the FP64
+    oracle's full-schedule reconstruction at its stored samples (three
+    z-slices and 4096 random voxels, tests/golden/paper_recon_oracle.npz,
+    written by tests/golden/make_paper_golden.py), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "paper_recon_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    v = vol.double().cpu().numpy()
+    ks = [int(k) for k in z["slices_k"]]
+    kji = z["voxels_kji"]
+    got = np.concatenate([v[ks].ravel(), v[kji[:, 0], kji[:, 1], kji[:, 2]]])
+    want = np.concatenate([z["slices"].astype(np.float64).ravel(), z["voxels"]])
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
 def main():
@@ -242,6 +307,8 @@ def main():
                                     "(different voxel size and 3-grid schedule; context only)"},
         "roofline": roofline,
     }
+    if args.workload == "paper":
+        line["config"]["rel_l2_vs_oracle_samples"] = oracle_samples_error(vol32)
     if not args.no_f16:
         for name, code in (("f16_storage", tfcb.F16), ("bf16_storage", tfcb.BF16)):
             volh, dth, _ = run(code, args.steps, 1, False)
@@ -251,6 +318,8 @@ def main():
                 "value": round(n_iters * args.steps / dth, 3), "unit": "TF iterations/s",
                 "ms_per_step": round(dth / args.steps * 1e3, 3),
                 "rel_l2_vs_f32": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
+            if args.workload == "paper":
+                line["config"][name]["rel_l2_vs_oracle_samples"] = oracle_samples_error(volh)
     if not args.no_pair:
         # the paper's own operators in the same schedule (section 2.2.1, Eq. (3))
         volp, dtp, repp = run(tfcb.F32, args.steps, 1, True, op_pair=1)

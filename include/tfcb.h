@@ -18,9 +18,13 @@
  *    null stream).  The library never allocates or frees device memory: the
  *    caller owns every buffer, including the workspace, which must be
  *    256-byte aligned and at least the size the matching *_workspace_size
- *    function reports.  Caller pointers are not kept after a call returns.
+ *    function reports.  Volume and projection buffers need only be aligned
+ *    to their element size (4 bytes for FP32, 2 for FP16/BF16).  Caller
+ *    pointers are not kept after a call returns.
  *  - Operator calls (project, backproject, framelet_shrink, restrict,
- *    prolong, cgls) are asynchronous on `stream`.  tfcb_reconstruct
+ *    prolong) are asynchronous on `stream`: they never synchronise it, and
+ *    a host angle array is read before the call returns.  tfcb_cgls
+ *    synchronises `stream` only when stats is non-NULL; tfcb_reconstruct
  *    synchronises `stream` before it returns.
  *  - Calls are reentrant when they use distinct workspaces and streams.
  *  - Geometry conventions (the paper leaves them open): source at
@@ -238,9 +242,15 @@ tfcb_status tfcb_request_bytes(const tfcb_geometry* g, const tfcb_options* o, si
 tfcb_status tfcb_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
                                tfcb_server** out);
 /* Validates and queues a request; TFCB_ENOMEM if it can never fit the arena.
+ * stream: the caller's stream that produces proj (a hipStream_t as void*,
+ * NULL = the null stream).  An event is recorded on it here, and the
+ * request's first kernel waits for that event, so work enqueued on `stream`
+ * before this call (e.g. the upload or computation of proj) is complete
+ * before proj is read.  Work enqueued on it afterwards is not waited for.
+ * vol may be read by the caller once tfcb_server_poll reports DONE.
  * id: HOST output. */
 tfcb_status tfcb_server_submit(tfcb_server* s, const tfcb_geometry* g, const tfcb_options* o,
-                               const float* proj, float* vol, uint64_t* id);
+                               const float* proj, float* vol, void* stream, uint64_t* id);
 /* Non-blocking: retires finished requests, admits queued ones, and enqueues
  * the next outer iteration of each active request (at most two iterations
  * ahead of the device per request).  n_active, n_queued: nullable HOST. */

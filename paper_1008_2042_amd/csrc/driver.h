@@ -106,9 +106,12 @@ tfcb_status validate_options(const tfcb_options* o) {
   return TFCB_OK;
 }
 
-tfcb_status check_ptr(const void* p, const char* name) {
+// Caller data buffers (volumes, projections) need element alignment only:
+// every kernel that reads them with wider vectors reads an internal copy.
+tfcb_status check_ptr(const void* p, const char* name, size_t elem_bytes) {
   if (!p) return fail(TFCB_EINVAL, "%s is NULL", name);
-  if (reinterpret_cast<uintptr_t>(p) % 2 != 0) return fail(TFCB_EINVAL, "%s is misaligned", name);
+  if (reinterpret_cast<uintptr_t>(p) % elem_bytes != 0)
+    return fail(TFCB_EINVAL, "%s is not aligned to its %zu-byte elements", name, elem_bytes);
   return TFCB_OK;
 }
 
@@ -139,6 +142,26 @@ tfcb_geometry coarse_of(const tfcb_geometry& f, bool bin) {
     c.dv = 2.0 * f.dv;
   }
   return c;
+}
+
+// Every grid of the schedule must pass the geometry checks (a coarser grid
+// is larger in mm: ceil sizes at twice the voxel), and a detector binned
+// 2 x 2 for the next-coarser grid must have even sizes, so each coarse pixel
+// centre is the mean of the four fine centres it averages.
+tfcb_status validate_schedule(const tfcb_geometry& g, const tfcb_options& o) {
+  tfcb_geometry cur = g;
+  for (int l = 1; l < o.n_grids; ++l) {
+    if (o.bin_coarse_detector && (cur.nu % 2 != 0 || cur.nv % 2 != 0))
+      return fail(TFCB_EUNSUPPORTED,
+                  "2x2 detector binning needs even detector sizes on every grid but the "
+                  "coarsest (grid %d is %d x %d)", l - 1, cur.nu, cur.nv);
+    cur = coarse_of(cur, o.bin_coarse_detector != 0);
+    const tfcb_status st = validate_geometry(&cur);
+    if (st != TFCB_OK)
+      return fail(st, "coarse grid %d (%d x %d x %d): %s", l, cur.nx, cur.ny, cur.nz,
+                  g_last_error.c_str());
+  }
+  return TFCB_OK;
 }
 
 // Sequential carving of a workspace into aligned sub-buffers.
@@ -172,7 +195,6 @@ struct GridBufs {
 struct Plan {
   int n_grids = 1;
   GridBufs grid[4];
-  double* angles = nullptr;
   CglsScalars* sc = nullptr;
   int* flag = nullptr;  // non-finite flag + 1024 doubles of partials
   size_t bytes = 0;
@@ -184,7 +206,6 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
   Carver cv(ws);
   const size_t es = dtype_size(o.storage);
   P.n_grids = o.n_grids;
-  P.angles = static_cast<double*>(cv.take(sizeof(double) * g.n_views));
   P.sc = static_cast<CglsScalars*>(cv.take(sizeof(CglsScalars)));
   P.flag = static_cast<int*>(cv.take(8 + 1024 * sizeof(double)));
   tfcb_geometry cur = g;
@@ -217,26 +238,14 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
   P.bytes = cv.off;
 }
 
-// Device-side tables of one grid (angles already on the device or NULL),
-// and the zero pads of its padded direction copies (never written later).
+// Device-side tables of one grid (the view angles of b.geom, if any, are
+// read from the host array during this call), and the zero pads of its
+// padded direction copies (never written later).
 template <typename T>
-tfcb_status setup_grid(const GridBufs& b, const double* angles_dev, hipStream_t s) {
-  TFCB_HIP(launch_geom_tables(b.geom, angles_dev, b.views, b.cols, s));
+tfcb_status setup_grid(const GridBufs& b, hipStream_t s) {
+  TFCB_HIP(launch_geom_tables(b.geom, b.views, b.cols, s));
   TFCB_HIP(launch_fill(b.pN_elems, 0.f, static_cast<T*>(b.pN), s));
   TFCB_HIP(launch_fill(b.pT_elems, 0.f, static_cast<T*>(b.pT), s));
-  return TFCB_OK;
-}
-
-tfcb_status upload_angles(const tfcb_geometry& g, double* dst, hipStream_t s,
-                          const double** out) {
-  if (!g.angles) {
-    *out = nullptr;
-    return TFCB_OK;
-  }
-  TFCB_HIP(hipMemcpyAsync(dst, g.angles, sizeof(double) * g.n_views, hipMemcpyHostToDevice, s));
-  // the host array is only guaranteed to live for the duration of the call
-  TFCB_HIP(hipStreamSynchronize(s));
-  *out = dst;
   return TFCB_OK;
 }
 
@@ -376,11 +385,9 @@ tfcb_status run_framelet(const tfcb_geometry& g, int levels, float lambda, int p
 template <typename T>
 tfcb_status reconstruct_t(const tfcb_geometry& g, const tfcb_options& o, const float* proj,
                           float* vol, const Plan& P, hipStream_t s, tfcb_report* rep) {
-  const double* ang = nullptr;
-  TFCB_TRY(upload_angles(g, P.angles, s, &ang));
   TFCB_HIP(launch_cgls_reset(P.sc, s));
   const int ng = o.n_grids;
-  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_grid<T>(P.grid[l], ang, s));
+  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_grid<T>(P.grid[l], s));
   // projections of every grid: the finest converted to the storage type,
   // coarser ones binned (or copied) from the next finer
   TFCB_HIP((launch_cast<float, T>(npix(g), proj, static_cast<T*>(P.grid[0].g), s)));
@@ -478,7 +485,6 @@ tfcb_status dispatch(tfcb_dtype dt, F&& f) {
 
 size_t operator_ws_bytes(const tfcb_geometry& g, tfcb_dtype dt) {
   Carver cv(nullptr);
-  cv.take(sizeof(double) * g.n_views);
   cv.take(sizeof(ViewInfo) * g.n_views);
   cv.take(sizeof(ColInfo) * (size_t)g.n_views * g.nu);
   // project: the two padded copies; backproject: the prescaled projections

@@ -29,6 +29,7 @@ const char* tfcb_version(void) { return "tfcb 0.1 gfx950"; }
 tfcb_status tfcb_workspace_size(const tfcb_geometry* g, const tfcb_options* o, size_t* bytes) {
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_options(o));
+  TFCB_TRY(validate_schedule(*g, *o));
   if (!bytes) return fail(TFCB_EINVAL, "bytes is NULL");
   Plan P;
   make_plan(*g, *o, nullptr, P);
@@ -59,22 +60,19 @@ tfcb_status tfcb_project(const tfcb_geometry* g, tfcb_dtype dt, const void* vol,
                          void* ws, size_t ws_bytes, void* stream) {
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_dtype(dt));
-  TFCB_TRY(check_ptr(vol, "vol"));
-  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ptr(vol, "vol", dtype_size(dt)));
+  TFCB_TRY(check_ptr(proj, "proj", dtype_size(dt)));
   TFCB_TRY(check_ws(ws, ws_bytes, operator_ws_bytes(*g, dt)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(dt, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
     Carver cv(ws);
-    double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
     ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
     ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
     const size_t nN = pad_elems(g->ny, g->nx, g->nz), nT = pad_elems(g->nx, g->ny, g->nz);
     T* padN = static_cast<T*>(cv.take(nN * sizeof(T)));
     T* padT = static_cast<T*>(cv.take(nT * sizeof(T)));
-    const double* angd = nullptr;
-    TFCB_TRY(upload_angles(*g, ang, s, &angd));
-    TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
+    TFCB_HIP(launch_geom_tables(*g, views, cols, s));
     const GeomDev gd = make_geom_dev(*g);
     TFCB_HIP(launch_fill(nN, 0.f, padN, s));
     TFCB_HIP(launch_fill(nT, 0.f, padT, s));
@@ -90,20 +88,17 @@ tfcb_status tfcb_backproject(const tfcb_geometry* g, tfcb_dtype dt, const void* 
                              void* ws, size_t ws_bytes, void* stream) {
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_dtype(dt));
-  TFCB_TRY(check_ptr(vol, "vol"));
-  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ptr(vol, "vol", dtype_size(dt)));
+  TFCB_TRY(check_ptr(proj, "proj", dtype_size(dt)));
   TFCB_TRY(check_ws(ws, ws_bytes, operator_ws_bytes(*g, dt)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(dt, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
     Carver cv(ws);
-    double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
     ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
     ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
     T* rl = static_cast<T*>(cv.take(npix(*g) * sizeof(T)));
-    const double* angd = nullptr;
-    TFCB_TRY(upload_angles(*g, ang, s, &angd));
-    TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
+    TFCB_HIP(launch_geom_tables(*g, views, cols, s));
     const GeomDev gd = make_geom_dev(*g);
     TFCB_HIP(launch_prescale(gd, cols, views, static_cast<const T*>(proj), rl, s));
     TFCB_HIP(launch_backproject(gd, views, cols, (const T*)rl, static_cast<T*>(vol), nullptr,
@@ -118,22 +113,19 @@ tfcb_status tfcb_project_siddon(const tfcb_geometry* g, tfcb_dtype dt, const voi
                                 void* proj, void* ws, size_t ws_bytes, void* stream) {
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_dtype(dt));
-  TFCB_TRY(check_ptr(vol, "vol"));
-  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ptr(vol, "vol", dtype_size(dt)));
+  TFCB_TRY(check_ptr(proj, "proj", dtype_size(dt)));
   TFCB_TRY(check_ws(ws, ws_bytes, operator_ws_bytes(*g, dt)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(dt, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
     Carver cv(ws);
-    double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
     ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
     ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
     const size_t nN = pad_elems(g->ny, g->nx, g->nz), nT = pad_elems(g->nx, g->ny, g->nz);
     T* padN = static_cast<T*>(cv.take(nN * sizeof(T)));
     T* padT = static_cast<T*>(cv.take(nT * sizeof(T)));
-    const double* angd = nullptr;
-    TFCB_TRY(upload_angles(*g, ang, s, &angd));
-    TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
+    TFCB_HIP(launch_geom_tables(*g, views, cols, s));
     const GeomDev gd = make_geom_dev(*g);
     TFCB_HIP(launch_fill(nN, 0.f, padN, s));
     TFCB_HIP(launch_fill(nT, 0.f, padT, s));
@@ -150,19 +142,16 @@ tfcb_status tfcb_backproject_eq3(const tfcb_geometry* g, tfcb_dtype dt, const vo
                                  void* vol, void* ws, size_t ws_bytes, void* stream) {
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_dtype(dt));
-  TFCB_TRY(check_ptr(vol, "vol"));
-  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ptr(vol, "vol", dtype_size(dt)));
+  TFCB_TRY(check_ptr(proj, "proj", dtype_size(dt)));
   TFCB_TRY(check_ws(ws, ws_bytes, operator_ws_bytes(*g, dt)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(dt, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
     Carver cv(ws);
-    double* ang = static_cast<double*>(cv.take(sizeof(double) * g->n_views));
     ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
     ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
-    const double* angd = nullptr;
-    TFCB_TRY(upload_angles(*g, ang, s, &angd));
-    TFCB_HIP(launch_geom_tables(*g, angd, views, cols, s));
+    TFCB_HIP(launch_geom_tables(*g, views, cols, s));
     const GeomDev gd = make_geom_dev(*g);
     TFCB_HIP(launch_backproject_eq3(gd, views, static_cast<const T*>(proj), static_cast<T*>(vol),
                                     nullptr, nullptr, s));
@@ -176,8 +165,8 @@ tfcb_status tfcb_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t lev
   size_t need = 0;
   TFCB_TRY(tfcb_framelet_workspace_size(nx, ny, nz, levels, dt, &need));
   if (!std::isfinite(lambda) || lambda < 0.0) return fail(TFCB_EINVAL, "lambda must be >= 0");
-  TFCB_TRY(check_ptr(in, "in"));
-  TFCB_TRY(check_ptr(out, "out"));
+  TFCB_TRY(check_ptr(in, "in", dtype_size(dt)));
+  TFCB_TRY(check_ptr(out, "out", dtype_size(dt)));
   if (in == out) return fail(TFCB_EINVAL, "in and out must not alias");
   TFCB_TRY(check_ws(ws, ws_bytes, need));
   if ((double)nx * ny * nz >= 2147483647.0) return fail(TFCB_EUNSUPPORTED, "volume too large");
@@ -205,8 +194,8 @@ tfcb_status tfcb_cgls(const tfcb_geometry* g, const tfcb_options* o, void* x, co
   TFCB_TRY(validate_dtype(o->storage));
   if (o->cgls_steps < 1 || o->cgls_steps > 64) return fail(TFCB_EINVAL, "cgls_steps must be 1..64");
   if (o->op_pair != 0 && o->op_pair != 1) return fail(TFCB_EINVAL, "op_pair must be 0 or 1");
-  TFCB_TRY(check_ptr(x, "x"));
-  TFCB_TRY(check_ptr(proj, "proj"));
+  TFCB_TRY(check_ptr(x, "x", dtype_size(o->storage)));
+  TFCB_TRY(check_ptr(proj, "proj", dtype_size(o->storage)));
   tfcb_options one = *o;
   one.n_grids = 1;
   one.iters[0] = 1;
@@ -218,10 +207,8 @@ tfcb_status tfcb_cgls(const tfcb_geometry* g, const tfcb_options* o, void* x, co
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(o->storage, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
-    const double* ang = nullptr;
-    TFCB_TRY(upload_angles(*g, P.angles, s, &ang));
     TFCB_HIP(launch_cgls_reset(P.sc, s));
-    TFCB_TRY(setup_grid<T>(P.grid[0], ang, s));
+    TFCB_TRY(setup_grid<T>(P.grid[0], s));
     TFCB_TRY(run_cgls<T>(P.grid[0], P.sc, static_cast<T*>(x), static_cast<const T*>(proj),
                          o->cgls_steps, s));
     if (stats) {
@@ -239,8 +226,8 @@ tfcb_status tfcb_restrict_sino(const tfcb_geometry* fine, tfcb_dtype dt, const v
                                void* stream) {
   TFCB_TRY(validate_geometry(fine));
   TFCB_TRY(validate_dtype(dt));
-  TFCB_TRY(check_ptr(in, "in"));
-  TFCB_TRY(check_ptr(out, "out"));
+  TFCB_TRY(check_ptr(in, "in", dtype_size(dt)));
+  TFCB_TRY(check_ptr(out, "out", dtype_size(dt)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(dt, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
@@ -260,8 +247,8 @@ tfcb_status tfcb_prolong_vol(const tfcb_geometry* coarse, const tfcb_geometry* f
       !finite_pos(fine->dx) || !finite_pos(fine->dy) || !finite_pos(fine->dz))
     return fail(TFCB_EINVAL, "voxel sizes must be finite and > 0");
   TFCB_TRY(validate_dtype(dt));
-  TFCB_TRY(check_ptr(in, "in"));
-  TFCB_TRY(check_ptr(out, "out"));
+  TFCB_TRY(check_ptr(in, "in", dtype_size(dt)));
+  TFCB_TRY(check_ptr(out, "out", dtype_size(dt)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(dt, [&](auto tag) -> tfcb_status {
     using T = decltype(tag);
@@ -275,8 +262,9 @@ tfcb_status tfcb_reconstruct(const tfcb_geometry* g, const tfcb_options* o, cons
                              tfcb_report* report) {
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_options(o));
-  TFCB_TRY(check_ptr(proj, "proj"));
-  TFCB_TRY(check_ptr(vol, "vol"));
+  TFCB_TRY(validate_schedule(*g, *o));
+  TFCB_TRY(check_ptr(proj, "proj", sizeof(float)));
+  TFCB_TRY(check_ptr(vol, "vol", sizeof(float)));
   Plan P;
   make_plan(*g, *o, nullptr, P);
   TFCB_TRY(check_ws(ws, ws_bytes, P.bytes));

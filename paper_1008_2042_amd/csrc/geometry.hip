@@ -5,18 +5,26 @@
 
 namespace tfcb {
 
+// Views per launch whose angles travel inside the kernel arguments (1 KB),
+// so the caller's host array is read when the launch is enqueued and no
+// host-to-device copy or synchronisation is needed.
+constexpr int kAnglesPerLaunch = 128;
+
 struct GeomParams64 {
   double dx, dy, dz, du, dv, sad, sdd;
   int32_t nx, ny, nz, nu, nv, n_views;
   int32_t has_angles;
+  int32_t k0;  // first view of this launch
+  double ang[kAnglesPerLaunch];
 };
 
-__global__ void k_geom_tables(GeomParams64 g, const double* __restrict__ angles,
-                              ViewInfo* __restrict__ views, ColInfo* __restrict__ cols) {
+__global__ void k_geom_tables(GeomParams64 g, ViewInfo* __restrict__ views,
+                              ColInfo* __restrict__ cols) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
+  const int k = g.k0 + blockIdx.y;
   if (c >= g.nu) return;
-  const double th = g.has_angles ? angles[k] : 2.0 * M_PI * (double)k / (double)g.n_views;
+  const double th =
+      g.has_angles ? g.ang[blockIdx.y] : 2.0 * M_PI * (double)k / (double)g.n_views;
   const double cs = cos(th), sn = sin(th);
   const double sx = g.sad * cs, sy = g.sad * sn;
   const int step_x = fabs(cs) >= fabs(sn) - 1e-12;
@@ -69,17 +77,25 @@ __global__ void k_geom_tables(GeomParams64 g, const double* __restrict__ angles,
   cols[(size_t)k * g.nu + c] = ci;
 }
 
-hipError_t launch_geom_tables(const tfcb_geometry& g, const double* angles_dev, ViewInfo* views,
-                              ColInfo* cols, hipStream_t s) {
-  GeomParams64 p;
+hipError_t launch_geom_tables(const tfcb_geometry& g, ViewInfo* views, ColInfo* cols,
+                              hipStream_t s) {
+  GeomParams64 p{};
   p.dx = g.dx; p.dy = g.dy; p.dz = g.dz; p.du = g.du; p.dv = g.dv;
   p.sad = g.sad; p.sdd = g.sdd;
   p.nx = g.nx; p.ny = g.ny; p.nz = g.nz; p.nu = g.nu; p.nv = g.nv; p.n_views = g.n_views;
-  p.has_angles = angles_dev != nullptr;
-  dim3 block(64);
-  dim3 grid((g.nu + 63) / 64, g.n_views);
-  hipLaunchKernelGGL(k_geom_tables, grid, block, 0, s, p, angles_dev, views, cols);
-  return hipGetLastError();
+  p.has_angles = g.angles != nullptr;
+  for (int k0 = 0; k0 < g.n_views; k0 += kAnglesPerLaunch) {
+    const int n = g.n_views - k0 < kAnglesPerLaunch ? g.n_views - k0 : kAnglesPerLaunch;
+    p.k0 = k0;
+    if (g.angles)
+      for (int i = 0; i < n; ++i) p.ang[i] = g.angles[k0 + i];
+    dim3 block(64);
+    dim3 grid((g.nu + 63) / 64, n);
+    hipLaunchKernelGGL(k_geom_tables, grid, block, 0, s, p, views, cols);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace tfcb

@@ -77,9 +77,11 @@ struct Request {
   tfcb_options opts{};
   const float* proj = nullptr;
   float* vol = nullptr;
+  hipEvent_t ready_ev = nullptr;  // recorded on the producer stream at submit
   int state = RQ_QUEUED;
   tfcb_status result = TFCB_OK;
-  size_t off = 0, bytes = 0;
+  size_t need = 0;          // arena bytes the request needs
+  size_t off = 0, bytes = 0;  // its arena block while admitted (bytes 0 otherwise)
   Plan plan;
   int slot = -1;
   int grid = -1;  // current grid (0 = finest), -1 before the prologue
@@ -128,15 +130,11 @@ template <typename T>
 tfcb_status prologue(tfcb_server* S, Request& R) {
   hipStream_t s = S->streams[R.slot];
   const Plan& P = R.plan;
-  const double* ang = nullptr;
-  if (!R.angles.empty()) {
-    TFCB_HIP(hipMemcpyAsync(P.angles, R.angles.data(), sizeof(double) * R.angles.size(),
-                            hipMemcpyHostToDevice, s));
-    ang = P.angles;
-  }
+  // the projections are read only after the caller's work that produced them
+  TFCB_HIP(hipStreamWaitEvent(s, R.ready_ev, 0));
   TFCB_HIP(launch_cgls_reset(P.sc, s));
   const int ng = R.opts.n_grids;
-  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_grid<T>(P.grid[l], ang, s));
+  for (int l = 0; l < ng; ++l) TFCB_TRY(setup_grid<T>(P.grid[l], s));
   TFCB_HIP((launch_cast<float, T>(npix(R.geom), R.proj, static_cast<T*>(P.grid[0].g), s)));
   for (int l = 1; l < ng; ++l) {
     const GridBufs& f = P.grid[l - 1];
@@ -227,6 +225,10 @@ tfcb_status advance_any(tfcb_server* S, Request& R) {
 }
 
 void release_request(tfcb_server* S, Request& R) {
+  if (R.ready_ev) {
+    S->pool.push_back(R.ready_ev);
+    R.ready_ev = nullptr;
+  }
   for (hipEvent_t e : R.inflight) S->pool.push_back(e);
   R.inflight.clear();
   if (R.done_ev) {
@@ -283,12 +285,13 @@ tfcb_status tfcb_server_create(void* arena, size_t arena_bytes, int32_t max_slot
 }
 
 tfcb_status tfcb_server_submit(tfcb_server* S, const tfcb_geometry* g, const tfcb_options* o,
-                               const float* proj, float* vol, uint64_t* id) {
+                               const float* proj, float* vol, void* stream, uint64_t* id) {
   if (!S || !id) return fail(TFCB_EINVAL, "server or id is NULL");
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_options(o));
-  TFCB_TRY(check_ptr(proj, "proj"));
-  TFCB_TRY(check_ptr(vol, "vol"));
+  TFCB_TRY(validate_schedule(*g, *o));
+  TFCB_TRY(check_ptr(proj, "proj", sizeof(float)));
+  TFCB_TRY(check_ptr(vol, "vol", sizeof(float)));
   std::unique_ptr<Request> R(new Request());
   R->geom = *g;
   if (g->angles) {
@@ -301,10 +304,19 @@ tfcb_status tfcb_server_submit(tfcb_server* S, const tfcb_geometry* g, const tfc
   R->vol = vol;
   Plan P;
   make_plan(R->geom, R->opts, nullptr, P);
-  R->bytes = align_up(P.bytes);
-  if (R->bytes > S->arena.size())
-    return fail(TFCB_ENOMEM, "request needs %zu bytes, the arena holds %zu", R->bytes,
+  R->need = align_up(P.bytes);
+  if (R->need > S->arena.size())
+    return fail(TFCB_ENOMEM, "request needs %zu bytes, the arena holds %zu", R->need,
                 S->arena.size());
+  TFCB_HIP(get_event(S, &R->ready_ev));
+  {
+    const hipError_t e = hipEventRecord(R->ready_ev, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+      S->pool.push_back(R->ready_ev);
+      return fail(TFCB_EDEVICE, "hipEventRecord on the producer stream failed: %s",
+                  hipGetErrorString(e));
+    }
+  }
   R->id = S->next_id++;
   *id = R->id;
   S->queue.push_back(R->id);
@@ -340,10 +352,10 @@ tfcb_status tfcb_server_step(tfcb_server* S, int32_t* n_active, int32_t* n_queue
     if (slot < 0) break;
     Request& R = *S->reqs[S->queue.front()];
     size_t off = 0;
-    const size_t need = R.bytes;
-    if (!S->arena.alloc(need, &off)) break;
+    if (!S->arena.alloc(R.need, &off)) break;
     S->queue.pop_front();
     R.off = off;
+    R.bytes = R.need;
     make_plan(R.geom, R.opts, S->arena.base() + off, R.plan);
     R.slot = slot;
     S->slot_busy[slot] = 1;
@@ -400,6 +412,7 @@ tfcb_status tfcb_server_cancel(tfcb_server* S, uint64_t id) {
         S->queue.erase(q);
         break;
       }
+    release_request(S, R);  // holds only its producer event
   } else if (R.state == RQ_RUNNING) {
     TFCB_HIP(hipStreamSynchronize(S->streams[R.slot]));
     release_request(S, R);

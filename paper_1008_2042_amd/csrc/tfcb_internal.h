@@ -162,8 +162,11 @@ __device__ __forceinline__ float ray_length(const GeomDev& g, const ViewInfo& vi
 
 // ------------------------------------------------------------ launchers
 // All return hipGetLastError() of the launch.
-hipError_t launch_geom_tables(const tfcb_geometry& g, const double* angles_dev, ViewInfo* views,
-                              ColInfo* cols, hipStream_t s);
+// Per-view and per-column tables of g; the view angles (g.angles, a host
+// array, or NULL for 2 pi k / n_views) are passed by value in the launches'
+// arguments, so the host array may be released as soon as this returns.
+hipError_t launch_geom_tables(const tfcb_geometry& g, ViewInfo* views, ColInfo* cols,
+                              hipStream_t s);
 
 // P of a volume given as its two zero-padded copies (padN native, padT
 // transposed).  mode 0: out = P vol.  mode 1: r = g - P vol, rl = l * r,

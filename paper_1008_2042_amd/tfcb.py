@@ -97,7 +97,7 @@ def load(path: str = LIB_PATH):
         "tfcb_reconstruct": ([G, O, vp, vp, vp, sz, vp, ctypes.POINTER(Report)], i32),
         "tfcb_request_bytes": ([G, O, psz], i32),
         "tfcb_server_create": ([vp, sz, i32, ctypes.POINTER(vp)], i32),
-        "tfcb_server_submit": ([vp, G, O, vp, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
+        "tfcb_server_submit": ([vp, G, O, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
         "tfcb_server_step": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "tfcb_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                               ctypes.POINTER(i32)], i32),
@@ -340,13 +340,16 @@ class Server:
                                          ctypes.byref(n)))
         return n.value
 
-    def submit(self, g, proj, opts: Options, out=None) -> int:
+    def submit(self, g, proj, opts: Options, out=None, stream=None) -> int:
+        """Queues a request; its kernels wait for the work already enqueued
+        on `stream` (default: torch's current stream), which produced proj."""
         torch = _torch()
         if out is None:
             out = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=proj.device)
         rid = ctypes.c_uint64(0)
         _check(load().tfcb_server_submit(self._h, ctypes.byref(geometry(g)), ctypes.byref(opts),
-                                         _ptr(proj), _ptr(out), ctypes.byref(rid)))
+                                         _ptr(proj), _ptr(out), _stream(stream),
+                                         ctypes.byref(rid)))
         self._keep[rid.value] = (proj, out)
         return rid.value
 

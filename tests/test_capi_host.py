@@ -118,3 +118,37 @@ def test_product_path_does_not_reference_the_oracle():
                 with open(os.path.join(dirpath, f)) as fh:
                     text = fh.read()
                 assert "import oracle" not in text and "tf_oracle" not in text, f
+
+
+def test_every_grid_of_the_schedule_is_validated():
+    """Coarser grids are checked like the finest: a detector binned 2 x 2
+    for the next grid must have even sizes (each coarse pixel centre is then
+    the mean of the four it averages), and a coarse grid (ceil sizes, twice
+    the voxel, so larger in mm) must stay inside the source orbit."""
+    lib = _lib()
+    n = ctypes.c_size_t(0)
+    base = inputs.Geometry(48, 40, 12, 1.5, 1.5, 1.5, 96, 48, 2.0, 2.0, n_views=20)
+    o2 = tfcb.options(5e-4, [2, 2])
+    assert lib.tfcb_workspace_size(ctypes.byref(tfcb.geometry(base)), ctypes.byref(o2),
+                                   ctypes.byref(n)) == 0
+    for nu, nv in ((97, 48), (96, 47)):
+        odd = inputs.Geometry(48, 40, 12, 1.5, 1.5, 1.5, nu, nv, 2.0, 2.0, n_views=20)
+        assert lib.tfcb_workspace_size(ctypes.byref(tfcb.geometry(odd)), ctypes.byref(o2),
+                                       ctypes.byref(n)) == tfcb.EUNSUPPORTED
+        assert b"even" in lib.tfcb_last_error()
+        # one grid, or no binning: nothing is binned, so odd sizes are fine
+        for o in (tfcb.options(5e-4, [2]), tfcb.options(5e-4, [2, 2], bin_detector=False)):
+            assert lib.tfcb_workspace_size(ctypes.byref(tfcb.geometry(odd)), ctypes.byref(o),
+                                           ctypes.byref(n)) == 0
+    # a fine grid just inside the orbit whose two-grid coarse grid is not:
+    # fine half-diagonal (0.5*181 + 2) * 1.0 * sqrt(2) = 130.8 < 140, coarse
+    # (0.5*91 + 2) * 2.0 * sqrt(2) = 134.4 ... with 3 grids (0.5*46 + 2) * 4 * sqrt(2) = 141.4
+    wide = inputs.Geometry(181, 181, 8, 1.0, 1.0, 1.0, 64, 16, 1.0, 1.0, sad=140.0, sdd=210.0,
+                           n_views=8)
+    o1 = tfcb.options(5e-4, [2])
+    assert lib.tfcb_workspace_size(ctypes.byref(tfcb.geometry(wide)), ctypes.byref(o1),
+                                   ctypes.byref(n)) == 0
+    o3 = tfcb.options(5e-4, [1, 1, 1])
+    assert lib.tfcb_workspace_size(ctypes.byref(tfcb.geometry(wide)), ctypes.byref(o3),
+                                   ctypes.byref(n)) == tfcb.EINVAL
+    assert b"coarse grid 2" in lib.tfcb_last_error()

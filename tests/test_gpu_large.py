@@ -91,3 +91,40 @@ def test_large_reconstruction_shortened(storage):
     assert np.all(np.isfinite(v)) and v.min() >= 0.0
     assert rep["iters_done"] == [1, 1, 1]
     assert rep["resid2_last"] < 0.5 * float(torch.sum(y.double() ** 2))
+
+
+@pytest.mark.timeout(900)
+def test_large_coarsest_grid_iteration_whole_volume():
+    """One full outer iteration of Algorithm A2 (3 CGLS steps, two-level
+    framelet shrink, positivity) on the coarsest grid of the large workload's
+    3-grid schedule (128x128x64 at 2 mm, 360 views of the twice-binned
+    256x192 detector at 1.552 mm), from zero, over the whole volume against
+    the FP64 oracle: FP32 within 1e-3, FP16 storage reported (guard 1e-2).
+    The data are exact chords through the workload's 40-ellipsoid phantom
+    with Poisson noise (I0 = 5e4), generated on that geometry."""
+    dev = _dev()
+    gf = LARGE["geom"]
+    g = inputs.Geometry(gf.nx // 4, gf.ny // 4, gf.nz // 4, 4 * gf.dx, 4 * gf.dy, 4 * gf.dz,
+                        gf.nu // 4, gf.nv // 4, 4 * gf.du, 4 * gf.dv, sad=gf.sad, sdd=gf.sdd,
+                        n_views=gf.n_views)
+    announce("large coarsest-grid data %dx%dx%d, %d views of %dx%d"
+             % (g.nx, g.ny, g.nz, g.n_views, g.nu, g.nv))
+    clean = inputs.analytic_projection_torch(g, inputs.phantom_for(LARGE), dev)
+    y = inputs.poisson_log_torch(clean, LARGE["noise"][0], LARGE["noise"][1]).cpu().numpy()
+    del clean
+    announce("FP64 oracle: one outer iteration on %d threads" % oracle.num_threads())
+    want, orep = oracle.reconstruct(g, y, LARGE["lam"], [1], LARGE["cgls_steps"],
+                                    LARGE["framelet_levels"])
+    yd = torch.tensor(y, dtype=torch.float32, device=dev)
+    for name, code, bound in (("f32", tfcb.F32, 1e-3), ("f16", tfcb.F16, 1e-2)):
+        announce("large coarsest-grid iteration %s" % name)
+        got, rep = tfcb.reconstruct(g, yd, LARGE["lam"], [1], LARGE["cgls_steps"],
+                                    LARGE["framelet_levels"], storage=code)
+        v = got.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(v))
+        e = float(np.linalg.norm(v - want) / np.linalg.norm(want))
+        print("large coarsest grid, one outer iteration, %s storage: rel L2 vs FP64 oracle %.3e,"
+              " max abs %.3e; resid2 GPU %.6e oracle %.6e"
+              % (name, e, float(np.abs(v - want).max()), rep["resid2_last"],
+                 orep["resid2_last"]), flush=True)
+        assert e <= bound, (name, e)

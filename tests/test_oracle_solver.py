@@ -223,8 +223,21 @@ def test_exact_nonnegative_solution_is_a_fixed_point():
 
 
 def test_golden_momentum_sequence_closed_form():
+    """Every entry of the A2 table against Algorithm A2's recursion, and the
+    recursion against its closed forms: t(1) = (1 + sqrt 5) / 2, and each
+    t(k+1) is the positive root of t^2 - t = t(k)^2 (the quadratic the
+    update solves), so t(k+1)^2 - t(k+1) - t(k)^2 = 0."""
     t = GOLD["a2_momentum"]["t"]
-    assert t[1] == pytest.approx((1 + math.sqrt(5)) / 2, abs=1e-15)
     c = GOLD["a2_momentum"]["coefficient"]
+    assert len(t) == len(c) >= 6
+    t_prev, t_cur = 1.0, 1.0
+    for k in range(len(t)):
+        assert t[k] == pytest.approx(t_cur, rel=1e-15, abs=0)
+        assert c[k] == pytest.approx((t_prev - 1.0) / t_cur, rel=1e-15, abs=1e-300)
+        t_prev, t_cur = t_cur, 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * t_cur * t_cur))
+    assert t[1] == pytest.approx((1 + math.sqrt(5)) / 2, abs=1e-15)
+    for k in range(len(t) - 1):
+        assert t[k + 1] ** 2 - t[k + 1] - t[k] ** 2 == pytest.approx(0.0, abs=1e-13)
     assert c[0] == 0.0 and c[1] == 0.0
     assert c[2] == pytest.approx(0.281753, abs=1e-6) and c[3] == pytest.approx(0.434043, abs=1e-6)
+    assert c[4] == pytest.approx(0.531064, abs=1e-6)
