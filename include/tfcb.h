@@ -159,6 +159,25 @@ tfcb_status tfcb_project_siddon(const tfcb_geometry* g, tfcb_dtype dt, const voi
 tfcb_status tfcb_backproject_eq3(const tfcb_geometry* g, tfcb_dtype dt, const void* proj,
                                  void* vol, void* ws, size_t ws_bytes, void* stream);
 
+/* vol = P^T proj exactly as tfcb_backproject computes it (same kernels, same
+ * result bit for bit), for callers that cannot allocate device memory: code
+ * under stream capture, tight serving loops, hosts that forbid hipMalloc.
+ * Instead of a workspace it uses a static device array of
+ * TFCB_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; the call allocates nothing (no hipMalloc, hipFree
+ * or allocating library routine).  The geometry's scratch need (32 B per
+ * view, 32 B per detector column and view, one stored element per
+ * projection pixel, each rounded up to 256 B) must fit: larger geometries
+ * return TFCB_EUNSUPPORTED with nothing enqueued (the 512x512x70 workload's
+ * 40 x 384 x 512 projections need 32.1 MB in FP32).  Every call on one GPU
+ * shares that GPU's array: calls whose work overlaps on the device (on
+ * different streams, or from different threads) race and give undefined
+ * results; calls on one stream are ordered and safe.  proj, vol: device,
+ * storage dt; asynchronous on `stream`. */
+#define TFCB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tfcb_status tfcb_backproject_noalloc(const tfcb_geometry* g, tfcb_dtype dt, const void* proj,
+                                     void* vol, void* stream);
+
 /* out = H(W^T T_lambda W in) (section 2.1: the 27-band piecewise-linear
  * tight frame, the vector shrinkage of Eq. (2), positivity H when
  * positivity = 1).  W is convolution with half-sample symmetric extension and

@@ -23,7 +23,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENUMERIC, EBUSY = 0, -1, -2, -3, -4, 
 EXPORTS = [
     "tfcb_status_str", "tfcb_last_error", "tfcb_version",
     "tfcb_workspace_size", "tfcb_operator_workspace_size", "tfcb_framelet_workspace_size",
-    "tfcb_project", "tfcb_backproject", "tfcb_project_siddon", "tfcb_backproject_eq3",
+    "tfcb_project", "tfcb_backproject", "tfcb_backproject_noalloc", "tfcb_project_siddon",
+    "tfcb_backproject_eq3",
     "tfcb_framelet_shrink", "tfcb_cgls",
     "tfcb_restrict_sino", "tfcb_prolong_vol", "tfcb_reconstruct",
     "tfcb_request_bytes", "tfcb_server_create", "tfcb_server_submit", "tfcb_server_step",
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
         "tfcb_framelet_workspace_size": ([i32, i32, i32, i32, i32, psz], i32),
         "tfcb_project": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_backproject": ([G, i32, vp, vp, vp, sz, vp], i32),
+        "tfcb_backproject_noalloc": ([G, i32, vp, vp, vp], i32),
         "tfcb_project_siddon": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_backproject_eq3": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_framelet_shrink": ([i32, i32, i32, i32, dbl, i32, i32, vp, vp, vp, sz, vp], i32),
@@ -212,6 +214,21 @@ def backproject(g, proj, out=None, ws=None, stream=None):
         ws = _workspace(need, proj.device)
     _check(load().tfcb_backproject(ctypes.byref(geometry(g)), dt, _ptr(proj), _ptr(out), _ptr(ws),
                                    ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def backproject_noalloc(g, proj, out=None, stream=None):
+    """vol = P^T proj through the entry point that allocates nothing (its
+    scratch is the library's static per-GPU array)."""
+    torch = _torch()
+    dt = dtype_code(proj.dtype)
+    if out is None:
+        out = torch.empty((g.nz, g.ny, g.nx), dtype=proj.dtype, device=proj.device)
+    _check(load().tfcb_backproject_noalloc(ctypes.byref(geometry(g)), dt, _ptr(proj), _ptr(out),
+                                           _stream(stream)))
     return out
 
 
