@@ -168,6 +168,65 @@ def cpu_baseline(cfg, y):
                      "omp_threads": oracle.num_threads()}}
 
 
+LARGE_WORKLOAD = ("large single TF reconstruction: 512x512x256 volume at 0.5 mm, 360 views, "
+                  "1024x768 detector at 0.388 mm, 3-grid multigrid 5+10+15 iterations, "
+                  "3 CGLS steps, 2-level framelet, lambda 5e-4, 40-ellipsoid phantom, "
+                  "Poisson I0=5e4")
+
+
+def large_data(cfg, dev):
+    """283 M rays: exact chords evaluated on the device in FP64, then Poisson
+    noise, stored FP32."""
+    from paper_1008_2042_amd import inputs
+    clean = inputs.analytic_projection_torch(cfg["geom"], inputs.phantom_for(cfg), dev)
+    yd = inputs.poisson_log_torch(clean, cfg["noise"][0], cfg["noise"][1]).float()
+    del clean
+    return yd
+
+
+def load_counters(kernel_idx: int):
+    """The committed counter figures of a kernel (traffic.json), if they were
+    taken on its current source; else {}."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        t = json.load(fh)
+    ent = t.get(KERNEL_SOURCES[kernel_idx])
+    if not ent or ent.get("source_hash") != source_hash([KERNEL_SOURCES[kernel_idx]]):
+        return {}
+    return ent
+
+
+def kernel_fractions(g, avg_ms, samples):
+    """Per kernel of the fine grid: the HBM fraction of its compulsory bytes
+    (P: volume + projections; P^T: the same; framelet: 16 B per voxel in
+    FP32), the HBM-side traffic rate from the committed counters, and the
+    VALU issue fraction (SQ_INSTS_VALU per launch over one wave instruction
+    per clock per CU at 2.4 GHz, the rate of non-packed FP32 code)."""
+    V, S = g.nx * g.ny * g.nz * 4.0, g.n_views * g.nu * g.nv * 4.0
+    compulsory = [V + S, V + S, 16.0 * g.nx * g.ny * g.nz]
+    out = {}
+    for i, name in enumerate(KERNEL_NAMES):
+        t = avg_ms[i] * 1e-3
+        if t <= 0:
+            continue
+        ent = load_counters(i)
+        d = {"compulsory_bytes": int(compulsory[i]),
+             "hbm_frac_compulsory": round(compulsory[i] / t / 8e12, 4)}
+        if ent.get("bytes_per_launch"):
+            d["traffic_bytes"] = ent["bytes_per_launch"]
+            d["traffic_GBps"] = round(ent["bytes_per_launch"] / t / 1e9, 1)
+            d["traffic_frac_of_8TBps"] = round(ent["bytes_per_launch"] / t / 8e12, 4)
+        if ent.get("valu_insts_per_launch"):
+            d["valu_insts_per_launch"] = ent["valu_insts_per_launch"]
+            d["valu_issue_frac"] = round(ent["valu_insts_per_launch"] / t / (256 * 2.4e9), 4)
+            if i == 0:
+                d["lane_valu_per_sample"] = round(64.0 * ent["valu_insts_per_launch"] / samples, 2)
+        out[name] = d
+    return out
+
+
 def oracle_samples_error(vol):
     """Relative L2 error of a paper-scale GPU volume against the FP64
     oracle's full-schedule reconstruction at its stored samples (three
@@ -197,6 +256,9 @@ def main():
                     help="skip the run with the paper's own operators (Siddon P, Eq. (3) P^T)")
     ap.add_argument("--serving", type=int, default=16, metavar="N",
                     help="requests in the serving measurement (0 = skip; 64 = the full mix)")
+    ap.add_argument("--large", type=int, default=1, choices=[0, 1],
+                    help="with the paper workload, also time the large workload once in FP32 "
+                         "and FP16 storage (config.large)")
     ap.add_argument("--workload", default="paper", choices=["paper", "large"],
                     help="paper: 512x512x70, 40 views (default); large: 512x512x256, "
                          "360 views of 1024x768, 3 grids, 2-level framelet")
@@ -228,19 +290,15 @@ def main():
                     "3 CGLS steps, 1-level framelet, lambda 5e-4, 20-ellipsoid phantom, "
                     "Poisson I0=1e5")
     else:
-        # 283 M rays: the chords are evaluated on the device (FP64), then Poisson noise
-        clean = inputs.analytic_projection_torch(g, inputs.phantom_for(cfg), dev)
-        yd = inputs.poisson_log_torch(clean, cfg["noise"][0], cfg["noise"][1]).float()
-        del clean
+        yd = large_data(cfg, dev)
         y = None
         args.no_cpu_baseline = True
-        workload = ("large single TF reconstruction: 512x512x256 volume at 0.5 mm, 360 views, "
-                    "1024x768 detector at 0.388 mm, 3-grid multigrid 5+10+15 iterations, "
-                    "3 CGLS steps, 2-level framelet, lambda 5e-4, 40-ellipsoid phantom, "
-                    "Poisson I0=5e4")
+        args.large = 0
+        workload = LARGE_WORKLOAD
     n_iters = sum(cfg["iters"])
 
-    def run(storage, steps, warmup, profile, op_pair=0):
+    def run(storage, steps, warmup, profile, op_pair=0, cfg=cfg, yd=yd):
+        g = cfg["geom"]
         opts = tfcb.options(cfg["lam"], cfg["iters"], cfg["cgls_steps"], cfg["framelet_levels"],
                             storage=storage, profile=profile, op_pair=op_pair)
         ws = torch.empty(tfcb.workspace_size(g, opts), dtype=torch.uint8, device=dev)
@@ -257,6 +315,7 @@ def main():
             reps.append(rep)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        del ws
         return out.clone(), dt, reps
 
     vol32, dt32, reps = run(tfcb.F32, args.steps, args.warmup, True)
@@ -300,6 +359,7 @@ def main():
                    "coarse_grid_iters_per_s": round(cfg["iters"][0] / np.mean(
                        [r["seconds_per_grid"][0] for r in reps]), 3),
                    "kernel_avg_ms": {KERNEL_NAMES[i]: round(avg_ms[i], 4) for i in range(3)},
+                   "kernel_fractions": kernel_fractions(g, avg_ms, samples),
                    "kernel_share_fine_grid": {
                        n: round(float(kms[i] / max(np.sum(kms), 1e-30)), 3)
                        for i, n in enumerate(KERNEL_NAMES + ["other"])},
@@ -338,6 +398,29 @@ def main():
     if args.serving > 0 and args.workload == "paper":
         from paper_1008_2042_amd import serve
         line["config"]["serving"] = serve.serving_benchmark(n=args.serving, device=dev)
+    if args.large:
+        # the large single reconstruction, FP32 and FP16 storage, in the same run
+        lcfg = inputs.config("large")
+        lyd = large_data(lcfg, dev)
+        lg = lcfg["geom"]
+        vl32, dtl32, lreps = run(tfcb.F32, 1, 1, True, cfg=lcfg, yd=lyd)
+        del vl32
+        vl16, dtl16, _ = run(tfcb.F16, 1, 1, False, cfg=lcfg, yd=lyd)
+        del vl16, lyd
+        lk = np.sum([r["kernel_ms"] for r in lreps], axis=0)
+        lkn = np.sum([r["kernel_launches"] for r in lreps], axis=0)
+        nl = sum(lcfg["iters"])
+        line["config"]["large"] = {
+            "workload": LARGE_WORKLOAD,
+            "f32_s_per_recon": round(dtl32, 3), "f32_iters_per_s": round(nl / dtl32, 3),
+            "f16_storage_s_per_recon": round(dtl16, 3),
+            "f16_storage_iters_per_s": round(nl / dtl16, 3),
+            "seconds_per_grid_f32": [round(x, 4) for x in lreps[0]["seconds_per_grid"]],
+            "kernel_avg_ms_fine_grid_f32": {
+                KERNEL_NAMES[i]: round(float(lk[i] / lkn[i]) if lkn[i] else 0.0, 3)
+                for i in range(3)},
+            "note": "one timed reconstruction each after one untimed one"}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, y)
     print(json.dumps(line), flush=True)

@@ -50,7 +50,9 @@ def test_large_project_sampled_and_adjoint():
     pty = tfcb.backproject(g, y)
     lhs = float(torch.sum(pf.double() * y.double()))
     rhs = float(torch.sum(fd.double() * pty.double()))
-    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
+    err = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    print("large adjoint identity: relative mismatch %.2e" % err, flush=True)
+    assert err <= 1e-6
 
 
 @pytest.mark.parametrize("levels", [1, 2])
