@@ -53,6 +53,11 @@ class OrcOpts(ctypes.Structure):
                 ("op_pair", ctypes.c_int32)]
 
 
+class OrcTV(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("eps", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_steps", ctypes.c_int32)]
+
+
 class OrcReport(ctypes.Structure):
     _fields_ = [("resid2_last", ctypes.c_double), ("cgls_breakdowns", ctypes.c_int32),
                 ("iters_done", ctypes.c_int32 * 4)]
@@ -96,6 +101,13 @@ def _load():
                                 ctypes.c_int),
             "orc_tf_iterations": ([G, ctypes.POINTER(OrcOpts), _D, i32, _D,
                                    ctypes.POINTER(OrcReport)], ctypes.c_int),
+            "orc_tv_energy": ([i32, i32, i32, ctypes.POINTER(OrcTV), _D, _D], dbl),
+            "orc_tv_gradient": ([i32, i32, i32, ctypes.POINTER(OrcTV), _D, _D, _D], None),
+            "orc_rof": ([i32, i32, i32, ctypes.POINTER(OrcTV), _D, _D, ctypes.c_void_p],
+                        ctypes.c_int),
+            "orc_reconstruct_tv": ([G, ctypes.POINTER(OrcOpts), ctypes.POINTER(OrcTV), _D, _D,
+                                    ctypes.POINTER(OrcReport), ctypes.POINTER(i32)],
+                                   ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -355,3 +367,63 @@ def tf_iterations(g, proj, f0, n_iters, lam, cgls_steps=3, framelet_levels=1, mo
     _load().orc_tf_iterations(ctypes.byref(_geom(g)), ctypes.byref(o), proj, int(n_iters), vol,
                               ctypes.byref(rep))
     return vol, {"resid2_last": rep.resid2_last, "cgls_breakdowns": rep.cgls_breakdowns}
+
+
+# --------------------------------------------------------------------------
+# The TV comparison method (section 2.3)
+# --------------------------------------------------------------------------
+TV_EPS = 1e-5       # smoothing of |d| (1/mm), about 0.05 % of soft tissue
+TV_TOL = 1e-3       # the paper's 0.1 % stop
+TV_MAX_STEPS = 100
+
+
+def _tv(mu, eps=TV_EPS, tol=TV_TOL, max_steps=TV_MAX_STEPS):
+    return OrcTV(float(mu), float(eps), float(tol), int(max_steps))
+
+
+def tv_energy(x, f, mu, eps=TV_EPS):
+    """||f - x||^2 + mu TV_eps(f) (the ROF energy of section 2.3)."""
+    x = np.ascontiguousarray(x, np.float64)
+    nz, ny, nx = x.shape
+    return float(_load().orc_tv_energy(nx, ny, nz, ctypes.byref(_tv(mu, eps)), x,
+                                       _f64(f, x.shape)))
+
+
+def tv_gradient(x, f, mu, eps=TV_EPS):
+    x = np.ascontiguousarray(x, np.float64)
+    nz, ny, nx = x.shape
+    out = np.empty_like(x)
+    _load().orc_tv_gradient(nx, ny, nz, ctypes.byref(_tv(mu, eps)), x, _f64(f, x.shape), out)
+    return out
+
+
+def rof(x, mu, eps=TV_EPS, tol=TV_TOL, max_steps=TV_MAX_STEPS, history=False):
+    """The ROF sub-problem by adaptive gradient descent from f = x.  Returns
+    (f, accepted steps) or, with history, (f, steps, energies)."""
+    x = np.ascontiguousarray(x, np.float64)
+    nz, ny, nx = x.shape
+    f = np.empty_like(x)
+    hist = np.full(int(max_steps) + 1, np.nan)
+    n = _load().orc_rof(nx, ny, nz, ctypes.byref(_tv(mu, eps, tol, max_steps)), x, f,
+                        hist.ctypes.data_as(ctypes.c_void_p))
+    if history:
+        return f, int(n), hist[:n + 1]
+    return f, int(n)
+
+
+def reconstruct_tv(g, proj, mu, iters, cgls_steps=3, positivity=True, bin_detector=True,
+                   eps=TV_EPS, tol=TV_TOL, max_steps=TV_MAX_STEPS):
+    """The TV comparison method (x = CGLS(f), f = H(ROF(x))) in the multigrid
+    schedule; returns (volume, report dict with the accepted ROF steps)."""
+    proj = _f64(proj, _sino_shape(g))
+    o = _opts(0.0, len(iters), iters, cgls_steps, 1, False, positivity, bin_detector)
+    vol = np.empty(_vol_shape(g), np.float64)
+    rep = OrcReport()
+    steps = ctypes.c_int32(0)
+    rc = _load().orc_reconstruct_tv(ctypes.byref(_geom(g)), ctypes.byref(o),
+                                    ctypes.byref(_tv(mu, eps, tol, max_steps)), proj, vol,
+                                    ctypes.byref(rep), ctypes.byref(steps))
+    if rc != 0:
+        raise ValueError("orc_reconstruct_tv failed (%d)" % rc)
+    return vol, {"resid2_last": rep.resid2_last, "cgls_breakdowns": rep.cgls_breakdowns,
+                 "iters_done": list(rep.iters_done), "rof_steps": int(steps.value)}

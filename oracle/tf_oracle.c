@@ -17,6 +17,8 @@
  *   section 2.2.3             the coarse-to-fine multigrid schedule
  *   section 2.2.1, Eq. (3)    optionally, the paper's own operator pair:
  *                             Siddon's P with the closed-form backprojection
+ *   section 2.3               the TV comparison method: the same CGLS step,
+ *                             then the ROF sub-problem by gradient descent
  *
  * Readings where the paper is silent (each one is listed with its reason in
  * the design notes of the repository):
@@ -41,6 +43,10 @@
  *   - multigrid: coarse grids halve every axis (ceil), double the voxel size
  *     and stay centred; detector 2x2 binned (mean); prolongation is trilinear
  *     with the coarse index clamped to the grid; A2 restarts (t = 1) per grid.
+ *   - TV (section 2.3): the l1 norm of the gradient with forward differences
+ *     in index units, smoothed by eps; the ROF energy as printed, without a
+ *     factor 1/2 on the data term; the adaptive step and the stop rule are
+ *     stated at orc_rof; positivity after the sub-problem, as in A1.
  */
 #include "tf_oracle.h"
 
@@ -802,8 +808,144 @@ int orc_tf_iterations(const orc_geom* g, const orc_opts* o, const double* proj,
   return 0;
 }
 
-int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
-                    double* vol, orc_report* rep) {
+/* ------------------------------------------------------------------------- */
+/* The TV comparison method (section 2.3)                                     */
+/* ------------------------------------------------------------------------- */
+/* The ROF energy ||f - x||^2 + mu TV(f).  TV is the integral of the l1 norm
+ * of the gradient (section 2.3), discretised with forward differences in
+ * index units (d_a = f[i + e_a] - f[i] where voxel i + e_a exists) and
+ * smoothed, |d| ~ sqrt(d^2 + eps^2), so that gradient descent applies.  Per
+ * z-slice partial sums, added in slice order (deterministic). */
+double orc_tv_energy(int32_t nx, int32_t ny, int32_t nz, const orc_tv* tv,
+                     const double* x, const double* f) {
+  double* part = (double*)malloc(sizeof(double) * (size_t)nz);
+  const double e2 = tv->eps * tv->eps;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k) {
+    double data = 0.0, tvs = 0.0;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        int64_t q = ((int64_t)k * ny + j) * nx + i;
+        double r = f[q] - x[q];
+        data += r * r;
+        if (i + 1 < nx) {
+          double d = f[q + 1] - f[q];
+          tvs += sqrt(d * d + e2);
+        }
+        if (j + 1 < ny) {
+          double d = f[q + nx] - f[q];
+          tvs += sqrt(d * d + e2);
+        }
+        if (k + 1 < nz) {
+          double d = f[q + (int64_t)nx * ny] - f[q];
+          tvs += sqrt(d * d + e2);
+        }
+      }
+    part[k] = data + tv->mu * tvs;
+  }
+  double e = 0.0;
+  for (int k = 0; k < nz; ++k) e += part[k];
+  free(part);
+  return e;
+}
+
+/* dE/df: 2 (f - x) + mu sum_a [psi(d_a at i - e_a) - psi(d_a at i)], with
+ * psi(d) = d / sqrt(d^2 + eps^2) the derivative of the smoothed |d|. */
+void orc_tv_gradient(int32_t nx, int32_t ny, int32_t nz, const orc_tv* tv,
+                     const double* x, const double* f, double* grad) {
+  const double e2 = tv->eps * tv->eps;
+  const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        int64_t q = ((int64_t)k * ny + j) * nx + i;
+        double gq = 2.0 * (f[q] - x[q]);
+        double t = 0.0, d;
+        if (i + 1 < nx) { d = f[q + sx] - f[q]; t -= d / sqrt(d * d + e2); }
+        if (i > 0)      { d = f[q] - f[q - sx]; t += d / sqrt(d * d + e2); }
+        if (j + 1 < ny) { d = f[q + sy] - f[q]; t -= d / sqrt(d * d + e2); }
+        if (j > 0)      { d = f[q] - f[q - sy]; t += d / sqrt(d * d + e2); }
+        if (k + 1 < nz) { d = f[q + sz] - f[q]; t -= d / sqrt(d * d + e2); }
+        if (k > 0)      { d = f[q] - f[q - sz]; t += d / sqrt(d * d + e2); }
+        grad[q] = gq + tv->mu * t;
+      }
+}
+
+/* Gradient descent on the ROF energy from f = x (section 2.3).  The paper
+ * gives the rule only as "an adaptively adjusted step length" and the stop
+ * as a decrease under 0.1 %; the reading taken: the step s starts at 1/2
+ * (the exact minimiser of the data term alone); a trial f - s grad is
+ * accepted if it lowers the energy, otherwise s is halved and the trial
+ * repeated (at most 40 halvings, after which the descent ends); after an
+ * accepted step s doubles, up to 1/2; the descent ends after the first
+ * accepted step whose relative decrease is below tol, or after max_steps
+ * accepted steps. */
+int orc_rof(int32_t nx, int32_t ny, int32_t nz, const orc_tv* tv, const double* x,
+            double* f, double* energies) {
+  int64_t V = (int64_t)nx * ny * nz;
+  double* g = (double*)malloc(sizeof(double) * (size_t)V);
+  double* ft = (double*)malloc(sizeof(double) * (size_t)V);
+  memcpy(f, x, sizeof(double) * (size_t)V);
+  double E = orc_tv_energy(nx, ny, nz, tv, x, f);
+  if (energies) energies[0] = E;
+  double s = 0.5;
+  int steps = 0;
+  while (steps < tv->max_steps && E > 0.0) {
+    orc_tv_gradient(nx, ny, nz, tv, x, f, g);
+    int accepted = 0;
+    double Et = E;
+    for (int h = 0; h <= 40; ++h) {
+      for (int64_t q = 0; q < V; ++q) ft[q] = f[q] - s * g[q];
+      Et = orc_tv_energy(nx, ny, nz, tv, x, ft);
+      if (Et < E) {
+        accepted = 1;
+        break;
+      }
+      s *= 0.5;
+    }
+    if (!accepted) break;
+    double rel = (E - Et) / E;
+    memcpy(f, ft, sizeof(double) * (size_t)V);
+    E = Et;
+    ++steps;
+    if (energies) energies[steps] = E;
+    s = 2.0 * s < 0.5 ? 2.0 * s : 0.5;
+    if (rel < tv->tol) break;
+  }
+  free(g);
+  free(ft);
+  return steps;
+}
+
+/* n_iters outer iterations of the TV method on one grid from vol. */
+static int tv_iterations(const orc_geom* g, const orc_opts* o, const orc_tv* tv,
+                         const double* proj, int32_t n_iters, double* vol, orc_report* rep,
+                         int32_t* rof_steps) {
+  int64_t V = (int64_t)g->nx * g->ny * g->nz;
+  double* x = (double*)malloc(sizeof(double) * (size_t)V);
+  for (int k = 0; k < n_iters; ++k) {
+    memcpy(x, vol, sizeof(double) * (size_t)V);
+    double r2 = 0.0;
+    int broke = orc_cgls_pair(g, o->op_pair, x, proj, o->cgls_steps, &r2, NULL);
+    if (rep) {
+      rep->cgls_breakdowns += broke;
+      rep->resid2_last = r2;
+    }
+    int st = orc_rof(g->nx, g->ny, g->nz, tv, x, vol, NULL);
+    if (rof_steps) *rof_steps += st;
+    if (o->positivity)
+      for (int64_t i = 0; i < V; ++i)
+        if (vol[i] < 0.0) vol[i] = 0.0;
+  }
+  free(x);
+  return 0;
+}
+
+/* The coarse-to-fine schedule of section 2.2.3 around either method: the
+ * TF iteration (tv == NULL) or the TV one. */
+static int schedule(const orc_geom* g, const orc_opts* o, const orc_tv* tv, const double* proj,
+                    double* vol, orc_report* rep, int32_t* rof_steps) {
   int ng = o->n_grids;
   if (ng < 1 || ng > 4) return -1;
   orc_geom geo[4];
@@ -818,6 +960,7 @@ int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
     else memcpy(sino[l], sino[l - 1], sizeof(double) * (size_t)S);
   }
   if (rep) memset(rep, 0, sizeof(*rep));
+  if (rof_steps) *rof_steps = 0;
   double* cur = NULL;
   for (int l = ng - 1; l >= 0; --l) {
     int64_t V = (int64_t)geo[l].nx * geo[l].ny * geo[l].nz;
@@ -828,7 +971,8 @@ int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
       free(cur);
     }
     int it = o->iters[ng - 1 - l];
-    orc_tf_iterations(&geo[l], o, sino[l], it, f, rep);
+    if (tv) tv_iterations(&geo[l], o, tv, sino[l], it, f, rep, rof_steps);
+    else orc_tf_iterations(&geo[l], o, sino[l], it, f, rep);
     if (rep) rep->iters_done[ng - 1 - l] = it;
     cur = f;
   }
@@ -836,4 +980,16 @@ int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
   free(cur);
   for (int l = 1; l < ng; ++l) free(sino[l]);
   return 0;
+}
+
+int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
+                    double* vol, orc_report* rep) {
+  return schedule(g, o, NULL, proj, vol, rep, NULL);
+}
+
+int orc_reconstruct_tv(const orc_geom* g, const orc_opts* o, const orc_tv* tv,
+                       const double* proj, double* vol, orc_report* rep,
+                       int32_t* rof_steps) {
+  if (!tv || tv->mu < 0.0 || !(tv->eps > 0.0) || tv->max_steps < 0) return -1;
+  return schedule(g, o, tv, proj, vol, rep, rof_steps);
 }

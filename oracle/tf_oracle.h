@@ -109,4 +109,34 @@ int orc_reconstruct(const orc_geom* g, const orc_opts* o, const double* proj,
 int orc_tf_iterations(const orc_geom* g, const orc_opts* o, const double* proj,
                       int32_t n_iters, double* vol, orc_report* rep);
 
+/* The TV comparison method (section 2.3).  Energy of the ROF sub-problem
+ * ||f - x||^2 + mu TV(f), TV(f) the l1 norm of the gradient summed over
+ * voxels, smoothed: sum over voxels and axes of sqrt(d^2 + eps^2), d the
+ * forward difference to the next voxel along the axis (index units; no
+ * term past the last voxel). */
+typedef struct {
+  double mu;          /* TV weight mu_TV, >= 0 */
+  double eps;         /* smoothing of |d|, > 0 */
+  double tol;         /* stop when an accepted step lowers the energy by less
+                         than this fraction of it (the paper's 0.1 %) */
+  int32_t max_steps;  /* cap on accepted gradient steps per sub-problem */
+} orc_tv;
+
+double orc_tv_energy(int32_t nx, int32_t ny, int32_t nz, const orc_tv* tv,
+                     const double* x, const double* f);
+void orc_tv_gradient(int32_t nx, int32_t ny, int32_t nz, const orc_tv* tv,
+                     const double* x, const double* f, double* grad);
+/* The ROF sub-problem by gradient descent with an adaptive step, from f = x;
+ * returns the number of accepted steps; energies (nullable, max_steps + 1
+ * entries) receives the energy after each accepted step, [0] at f = x. */
+int orc_rof(int32_t nx, int32_t ny, int32_t nz, const orc_tv* tv, const double* x,
+            double* f, double* energies);
+/* The TV method inside the same multigrid schedule: per outer iteration
+ * x = CGLS(f), f = H(ROF(x)) (Algorithm A1 with step 2 replaced; momentum
+ * and the framelet fields of o are not used).  rof_steps (nullable) is the
+ * total number of accepted ROF steps. */
+int orc_reconstruct_tv(const orc_geom* g, const orc_opts* o, const orc_tv* tv,
+                       const double* proj, double* vol, orc_report* rep,
+                       int32_t* rof_steps);
+
 #endif
