@@ -101,6 +101,10 @@ def _load():
                                 ctypes.c_int),
             "orc_tf_iterations": ([G, ctypes.POINTER(OrcOpts), _D, i32, _D,
                                    ctypes.POINTER(OrcReport)], ctypes.c_int),
+            "orc_ramlak": ([i32, dbl], dbl),
+            "orc_fdk_filter": ([G, _D, _D], None),
+            "orc_fdk_backproject": ([G, _D, _D], None),
+            "orc_fdk": ([G, _D, _D], ctypes.c_int),
             "orc_tv_energy": ([i32, i32, i32, ctypes.POINTER(OrcTV), _D, _D], dbl),
             "orc_tv_gradient": ([i32, i32, i32, ctypes.POINTER(OrcTV), _D, _D, _D], None),
             "orc_rof": ([i32, i32, i32, ctypes.POINTER(OrcTV), _D, _D, ctypes.c_void_p],
@@ -427,3 +431,37 @@ def reconstruct_tv(g, proj, mu, iters, cgls_steps=3, positivity=True, bin_detect
         raise ValueError("orc_reconstruct_tv failed (%d)" % rc)
     return vol, {"resid2_last": rep.resid2_last, "cgls_breakdowns": rep.cgls_breakdowns,
                  "iters_done": list(rep.iters_done), "rof_steps": int(steps.value)}
+
+
+# --------------------------------------------------------------------------
+# FDK, the comparison baseline (textbook Feldkamp-Davis-Kress)
+# --------------------------------------------------------------------------
+def ramlak(n, dp):
+    """The Ram-Lak ramp kernel at integer lag n for spacing dp."""
+    return float(_load().orc_ramlak(int(n), float(dp)))
+
+
+def fdk_filter(g, proj):
+    """Cosine-weighted, ramp-filtered projections (one row at a time)."""
+    proj = _f64(proj, _sino_shape(g))
+    out = np.empty_like(proj)
+    _load().orc_fdk_filter(ctypes.byref(_geom(g)), proj, out)
+    return out
+
+
+def fdk_backproject(g, q):
+    q = _f64(q, _sino_shape(g))
+    vol = np.empty(_vol_shape(g), np.float64)
+    _load().orc_fdk_backproject(ctypes.byref(_geom(g)), q, vol)
+    return vol
+
+
+def fdk(g, proj):
+    """FDK reconstruction of an equally spaced full orbit."""
+    if getattr(g, "angles", None) is not None:
+        raise ValueError("FDK takes an equally spaced full orbit (angles None)")
+    proj = _f64(proj, _sino_shape(g))
+    vol = np.empty(_vol_shape(g), np.float64)
+    if _load().orc_fdk(ctypes.byref(_geom(g)), proj, vol) != 0:
+        raise ValueError("orc_fdk failed")
+    return vol

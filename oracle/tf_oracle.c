@@ -19,6 +19,7 @@
  *                             Siddon's P with the closed-form backprojection
  *   section 2.3               the TV comparison method: the same CGLS step,
  *                             then the ROF sub-problem by gradient descent
+ *   section 3 (comparisons)   FDK, the textbook filtered backprojection
  *
  * Readings where the paper is silent (each one is listed with its reason in
  * the design notes of the repository):
@@ -992,4 +993,101 @@ int orc_reconstruct_tv(const orc_geom* g, const orc_opts* o, const orc_tv* tv,
                        int32_t* rof_steps) {
   if (!tv || tv->mu < 0.0 || !(tv->eps > 0.0) || tv->max_steps < 0) return -1;
   return schedule(g, o, tv, proj, vol, rep, rof_steps);
+}
+
+/* ------------------------------------------------------------------------- */
+/* FDK, the comparison baseline of section 3 (the paper names it only):      */
+/* the textbook Feldkamp-Davis-Kress algorithm for a full circular orbit     */
+/* with equally spaced views and a flat detector.  Coordinates are scaled to */
+/* a virtual detector through the rotation axis: p = u SAD / SDD,            */
+/* zeta = v SAD / SDD, pitch dp = du SAD / SDD.                              */
+/*   1. weight each pixel by SAD / sqrt(SAD^2 + p^2 + zeta^2)                */
+/*      (= SDD / sqrt(SDD^2 + u^2 + v^2));                                   */
+/*   2. filter every detector row with the band-limited ramp (Ram-Lak)       */
+/*      kernel h, linear convolution with zero extension:                    */
+/*      Q(p_c) = dp sum_m w g(p_m) h((c - m) dp);                            */
+/*   3. backproject: f(x) = (pi / N) sum_views (SAD / U)^2 Q(p*, zeta*),     */
+/*      U = SAD - x.s_hat the source-to-voxel depth along the central ray,   */
+/*      p* = SAD (x.e_u) / U, zeta* = SAD z / U, Q bilinear between pixel    */
+/*      centres (zero off the detector).                                     */
+/* ------------------------------------------------------------------------- */
+/* The Ram-Lak kernel at lag n, spacing dp: the inverse Fourier transform of */
+/* |w| band-limited to |w| <= 1 / (2 dp), sampled at n dp.                   */
+double orc_ramlak(int32_t n, double dp) {
+  if (n == 0) return 1.0 / (4.0 * dp * dp);
+  if (n % 2 == 0) return 0.0;
+  return -1.0 / ((double)n * (double)n * M_PI * M_PI * dp * dp);
+}
+
+void orc_fdk_filter(const orc_geom* g, const double* proj, double* q) {
+  const int nu = g->nu, nv = g->nv;
+  const double mag = g->sad / g->sdd;
+  const double dp = g->du * mag;
+#pragma omp parallel
+  {
+    double* w = (double*)malloc(sizeof(double) * (size_t)nu);
+#pragma omp for schedule(static)
+    for (int64_t row = 0; row < (int64_t)g->n_views * nv; ++row) {
+      const int r = (int)(row % nv);
+      const double v = ((double)r - 0.5 * (nv - 1)) * g->dv;
+      const double* in = proj + row * nu;
+      for (int c = 0; c < nu; ++c) {
+        const double u = ((double)c - 0.5 * (nu - 1)) * g->du;
+        w[c] = in[c] * g->sdd / sqrt(g->sdd * g->sdd + u * u + v * v);
+      }
+      double* out = q + row * nu;
+      for (int c = 0; c < nu; ++c) {
+        double s = 0.0;
+        for (int m = 0; m < nu; ++m) s += w[m] * orc_ramlak(c - m, dp);
+        out[c] = dp * s;
+      }
+    }
+    free(w);
+  }
+}
+
+static double fdk_voxel(const orc_geom* g, const double* q, int i, int j, int k) {
+  const double x = ((double)i - 0.5 * (g->nx - 1)) * g->dx;
+  const double y = ((double)j - 0.5 * (g->ny - 1)) * g->dy;
+  const double z = ((double)k - 0.5 * (g->nz - 1)) * g->dz;
+  double s = 0.0;
+  for (int vw = 0; vw < g->n_views; ++vw) {
+    const double th = 2.0 * M_PI * (double)vw / (double)g->n_views;
+    const double cs = cos(th), sn = sin(th);
+    const double U = g->sad - (x * cs + y * sn);
+    const double t = -x * sn + y * cs;
+    /* detector position of the voxel centre, in pixel indices */
+    const double uc = g->sdd * t / U / g->du + 0.5 * (g->nu - 1);
+    const double vr = g->sdd * z / U / g->dv + 0.5 * (g->nv - 1);
+    const int c0 = (int)floor(uc), r0 = (int)floor(vr);
+    const double fc = uc - c0, fr = vr - r0;
+    double val = 0.0;
+    for (int dr = 0; dr < 2; ++dr)
+      for (int dc = 0; dc < 2; ++dc) {
+        const int c = c0 + dc, r = r0 + dr;
+        if (c < 0 || c >= g->nu || r < 0 || r >= g->nv) continue;
+        const double wgt = (dc ? fc : 1.0 - fc) * (dr ? fr : 1.0 - fr);
+        val += wgt * q[((int64_t)vw * g->nv + r) * g->nu + c];
+      }
+    s += (g->sad / U) * (g->sad / U) * val;
+  }
+  return M_PI / (double)g->n_views * s;
+}
+
+void orc_fdk_backproject(const orc_geom* g, const double* q, double* vol) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j)
+      for (int i = 0; i < g->nx; ++i)
+        vol[((int64_t)k * g->ny + j) * g->nx + i] = fdk_voxel(g, q, i, j, k);
+}
+
+int orc_fdk(const orc_geom* g, const double* proj, double* vol) {
+  if (g->angles) return -1; /* equally spaced full orbit only */
+  int64_t S = (int64_t)g->n_views * g->nu * g->nv;
+  double* q = (double*)malloc(sizeof(double) * (size_t)S);
+  orc_fdk_filter(g, proj, q);
+  orc_fdk_backproject(g, q, vol);
+  free(q);
+  return 0;
 }

@@ -139,4 +139,13 @@ int orc_reconstruct_tv(const orc_geom* g, const orc_opts* o, const orc_tv* tv,
                        const double* proj, double* vol, orc_report* rep,
                        int32_t* rof_steps);
 
+/* FDK (the paper's comparison baseline; textbook Feldkamp-Davis-Kress for an
+ * equally spaced full orbit, angles must be NULL): cosine weighting, a
+ * Ram-Lak ramp filter along detector rows, and the (SAD/U)^2-weighted
+ * voxel-driven backprojection with bilinear detector interpolation. */
+double orc_ramlak(int32_t n, double dp);
+void orc_fdk_filter(const orc_geom* g, const double* proj, double* q);
+void orc_fdk_backproject(const orc_geom* g, const double* q, double* vol);
+int orc_fdk(const orc_geom* g, const double* proj, double* vol);
+
 #endif
