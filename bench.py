@@ -32,6 +32,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X: 256 CU x 2.4 GHz x 256 FP32 flop/clk/
 FLOPS_PER_SAMPLE = 16.0          # algorithmic work of one (ray, plane) sample
 KERNEL_NAMES = ["P (k_project)", "P^T (k_backproject)", "framelet (k_framelet)"]
 KERNEL_SOURCES = ["project.hip", "backproject.hip", "framelet.hip"]
+TV_MU = 5e-4  # mu_TV of the TV comparison run (1/mm), tuned by hand as the paper does
 
 
 def plane_samples(g) -> int:
@@ -254,7 +255,12 @@ def main():
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16/BF16-storage runs")
     ap.add_argument("--no-pair", action="store_true",
                     help="skip the run with the paper's own operators (Siddon P, Eq. (3) P^T)")
-    ap.add_argument("--serving", type=int, default=16, metavar="N",
+    ap.add_argument("--no-tv", action="store_true",
+                    help="skip the TV comparison method (section 2.3) in the same schedule")
+    ap.add_argument("--quality", type=int, default=1, choices=[0, 1],
+                    help="run the image-quality protocols of section 3.2 (MTF, CNR against "
+                         "lambda, short scan) on the paper workload")
+    ap.add_argument("--serving", type=int, default=64, metavar="N",
                     help="requests in the serving measurement (0 = skip; 64 = the full mix)")
     ap.add_argument("--large", type=int, default=1, choices=[0, 1],
                     help="with the paper workload, also time the large workload once in FP32 "
@@ -297,21 +303,23 @@ def main():
         workload = LARGE_WORKLOAD
     n_iters = sum(cfg["iters"])
 
-    def run(storage, steps, warmup, profile, op_pair=0, cfg=cfg, yd=yd):
+    def run(storage, steps, warmup, profile, op_pair=0, cfg=cfg, yd=yd, regulariser=0):
         g = cfg["geom"]
-        opts = tfcb.options(cfg["lam"], cfg["iters"], cfg["cgls_steps"], cfg["framelet_levels"],
-                            storage=storage, profile=profile, op_pair=op_pair)
+        lam = TV_MU if regulariser else cfg["lam"]
+        opts = tfcb.options(lam, cfg["iters"], cfg["cgls_steps"], cfg["framelet_levels"],
+                            storage=storage, profile=profile, op_pair=op_pair,
+                            regulariser=regulariser)
         ws = torch.empty(tfcb.workspace_size(g, opts), dtype=torch.uint8, device=dev)
         out = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)
         kw = dict(cgls_steps=cfg["cgls_steps"], framelet_levels=cfg["framelet_levels"],
-                  storage=storage, out=out, ws=ws, op_pair=op_pair)
+                  storage=storage, out=out, ws=ws, op_pair=op_pair, regulariser=regulariser)
         for _ in range(warmup):
-            tfcb.reconstruct(g, yd, cfg["lam"], cfg["iters"], **kw)
+            tfcb.reconstruct(g, yd, lam, cfg["iters"], **kw)
         reps = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            _, rep = tfcb.reconstruct(g, yd, cfg["lam"], cfg["iters"], profile=profile, **kw)
+            _, rep = tfcb.reconstruct(g, yd, lam, cfg["iters"], profile=profile, **kw)
             reps.append(rep)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -395,6 +403,28 @@ def main():
                                                      "P^T (k_backproject_eq3)",
                                                      "framelet (k_framelet)"])},
             "rel_l2_vs_joseph_pair": float(torch.linalg.norm(a - b) / torch.linalg.norm(b))}
+    if not args.no_tv:
+        # the paper's comparison method (section 2.3) in the same schedule
+        volt, dtt, rept = run(tfcb.F32, args.steps, 1, True, regulariser=1)
+        kt = np.sum([r["kernel_ms"] for r in rept], axis=0)
+        ktn = np.sum([r["kernel_launches"] for r in rept], axis=0)
+        ng = len(cfg["iters"])
+        line["config"]["tv"] = {
+            "mu_tv": TV_MU, "value": round(n_iters * args.steps / dtt, 3),
+            "unit": "TV iterations/s", "ms_per_step": round(dtt / args.steps * 1e3, 3),
+            "s_per_iteration_by_grid_coarse_to_fine": [
+                round(float(np.mean([r["seconds_per_grid"][i] for r in rept])) / cfg["iters"][i],
+                      5) for i in range(ng)],
+            "tf_s_per_iteration_by_grid_coarse_to_fine": [
+                round(float(np.mean([r["seconds_per_grid"][i] for r in reps])) / cfg["iters"][i],
+                      5) for i in range(ng)],
+            "rof_steps_per_recon": float(np.mean([r["rof_steps"] for r in rept])),
+            "rof_ms_per_iteration_fine_grid": round(float(kt[2] / max(ktn[2], 1)), 4),
+            "note": "the paper reports TV/TF time per iteration 1.8/1.1, 5.1/4.1 and 17.7/15.2 s "
+                    "on its three grids (C1060)"}
+    if args.quality and args.workload == "paper":
+        from paper_1008_2042_amd import quality
+        line["config"]["image_quality"] = quality.run(dev)
     if args.serving > 0 and args.workload == "paper":
         from paper_1008_2042_amd import serve
         line["config"]["serving"] = serve.serving_benchmark(n=args.serving, device=dev)

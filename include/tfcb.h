@@ -93,6 +93,15 @@ typedef struct {
                                1 = the paper's pair, Siddon P with the Eq. (3)
                                backprojection in place of P^T
                                (tfcb_project_siddon / tfcb_backproject_eq3) */
+  int32_t regulariser;      /* step 2 of the outer iteration: 0 = the tight-frame
+                               shrinkage (Algorithms A1/A2); 1 = the TV
+                               comparison method of section 2.3: x = CGLS(f),
+                               f = H(ROF(x)) with lambda as mu_TV (momentum and
+                               framelet_levels unused); see tfcb_rof */
+  double tv_eps;            /* TV: smoothing of |d|, > 0 (1/mm) */
+  double tv_tol;            /* TV: stop the ROF descent at a relative energy
+                               decrease below this (the paper's 0.1 %: 1e-3) */
+  int32_t tv_max_steps;     /* TV: cap on accepted ROF steps, 0..100000 */
 } tfcb_options;
 
 typedef struct {
@@ -107,6 +116,7 @@ typedef struct {
    * transposes, reductions), launch count 0 */
   double kernel_ms[4];
   int32_t kernel_launches[4];
+  int32_t rof_steps;           /* TV: accepted ROF steps over the schedule */
 } tfcb_report;
 
 const char* tfcb_status_str(tfcb_status s);
@@ -190,6 +200,42 @@ tfcb_status tfcb_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t lev
                                  const void* in, void* out, void* ws, size_t ws_bytes,
                                  void* stream);
 
+/* FDK, the filtered-backprojection baseline the paper compares against
+ * (section 3; the paper gives no details, this is the textbook
+ * Feldkamp-Davis-Kress algorithm for an equally spaced full circular orbit
+ * and a flat detector): every pixel weighted by SDD / sqrt(SDD^2 + u^2 + v^2),
+ * every detector row convolved (zero outside the row) with the Ram-Lak ramp
+ * kernel of pitch dp = du SAD / SDD (dp times the sum; taps 1 / (4 dp^2) at
+ * lag 0, -1 / (pi n dp)^2 at odd lags n, 0 at even lags), then per voxel
+ * pi / n_views times the sum over views of (SAD / U)^2 times the filtered
+ * data interpolated bilinearly where the ray from the source through the
+ * voxel centre meets the detector (taps off the detector read 0), U = SAD -
+ * (x cos t + y sin t).  angles must be NULL; nu <= 8192.  proj, vol: device,
+ * storage dt; ws: tfcb_fdk_workspace_size bytes (the filtered projections in
+ * FP32); asynchronous on `stream`. */
+tfcb_status tfcb_fdk_workspace_size(const tfcb_geometry* g, size_t* bytes);
+tfcb_status tfcb_fdk(const tfcb_geometry* g, tfcb_dtype dt, const void* proj, void* vol,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* The ROF sub-problem of the TV comparison method (section 2.3):
+ * out = H(argmin_f ||f - x||^2 + mu TV(f)) approximated by gradient descent
+ * from f = x, where TV(f) sums sqrt(d^2 + eps^2) over the forward differences
+ * d of every voxel to its next neighbour along x, y and z (index units, no
+ * term past the last voxel; the l1 norm of the gradient, smoothed).  The
+ * step s starts at 1/2; a trial f - s grad that lowers the energy is taken
+ * and s doubles (up to 1/2), otherwise s halves and the trial is repeated
+ * (at most 40 times in a row); the descent ends after the first accepted
+ * step whose relative decrease is below tol, or after max_steps accepted
+ * steps.  Energies in FP64 on the device, arithmetic FP32.  H (negative
+ * voxels to 0) when positivity = 1.  x, out: device [nz][ny][nx], storage
+ * dt, must not alias; ws: tfcb_rof_workspace_size bytes.  Reads a stop flag
+ * back between chunks of descent steps, so the call synchronises `stream`.
+ * steps: nullable HOST output, the accepted steps. */
+tfcb_status tfcb_rof_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes);
+tfcb_status tfcb_rof(int32_t nx, int32_t ny, int32_t nz, double mu, double eps, double tol,
+                     int32_t max_steps, int32_t positivity, tfcb_dtype dt, const void* x,
+                     void* out, void* ws, size_t ws_bytes, void* stream, int32_t* steps);
+
 /* n CGLS steps (Appendix 1) warm-started from x, updated in place:
  * r = g - P x, s = P^T r, p = s, gamma = ||s||^2; then n times q = P p,
  * alpha = gamma / ||q||^2, x += alpha p, r -= alpha q and (except after the
@@ -226,14 +272,19 @@ tfcb_status tfcb_prolong_vol(const tfcb_geometry* coarse, const tfcb_geometry* f
  * proj: device FP32 [n_views][nv][nu] post-log data of the finest grid;
  * vol: device FP32 [nz][ny][nx] output (1/mm).  Synchronises `stream`.
  * report: nullable HOST pointer.  Returns TFCB_ENUMERIC (vol still written)
- * when the result holds a non-finite value. */
+ * when the result holds a non-finite value.  With regulariser = 1 the same
+ * schedule runs the TV comparison method of section 2.3 instead: per outer
+ * iteration x = CGLS(f) warm-started from f, then f = H(ROF(x)) as in
+ * tfcb_rof with mu = lambda. */
 tfcb_status tfcb_reconstruct(const tfcb_geometry* g, const tfcb_options* o, const float* proj,
                              float* vol, void* ws, size_t ws_bytes, void* stream,
                              tfcb_report* report);
 
 /* ---------------------------------------------------------------- serving */
 /* Continuous batching of whole reconstructions (the method of
- * tfcb_reconstruct, per request).  Requests of any geometry and options are
+ * tfcb_reconstruct, per request; the TF regulariser only: a request with
+ * regulariser = 1 is refused with TFCB_EUNSUPPORTED).  Requests of any
+ * geometry and options are
  * submitted at any time and admitted in arrival order as soon as one of
  * max_slots slots is free and the request's workspace (tfcb_request_bytes)
  * fits in the caller-owned device arena; each admitted request keeps all of

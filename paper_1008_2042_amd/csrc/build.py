@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libtfcb.so")
 BUILD = os.path.join(ROOT, "_build", "tfcb")
 
 SOURCES = ["geometry.hip", "project.hip", "backproject.hip", "framelet.hip", "vector.hip",
-           "paper_pair.hip", "engine.hip", "server.hip", "noalloc.hip"]
+           "paper_pair.hip", "engine.hip", "server.hip", "noalloc.hip", "tv.hip", "fdk.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TFCB_OFFLOAD_ARCH", "gfx950")

@@ -103,6 +103,16 @@ tfcb_status validate_options(const tfcb_options* o) {
     return fail(TFCB_EINVAL, "framelet_levels must be 1 or 2");
   TFCB_TRY(validate_dtype(o->storage));
   if (o->op_pair != 0 && o->op_pair != 1) return fail(TFCB_EINVAL, "op_pair must be 0 or 1");
+  if (o->regulariser != 0 && o->regulariser != 1)
+    return fail(TFCB_EINVAL, "regulariser must be 0 (tight frame) or 1 (TV)");
+  if (o->regulariser == 1) {
+    if (!std::isfinite(o->tv_eps) || !(o->tv_eps > 0.0))
+      return fail(TFCB_EINVAL, "tv_eps must be finite and > 0");
+    if (!std::isfinite(o->tv_tol) || o->tv_tol < 0.0)
+      return fail(TFCB_EINVAL, "tv_tol must be finite and >= 0");
+    if (o->tv_max_steps < 0 || o->tv_max_steps > 100000)
+      return fail(TFCB_EINVAL, "tv_max_steps must be 0..100000");
+  }
   return TFCB_OK;
 }
 
@@ -185,6 +195,8 @@ struct GridBufs {
   void *x0, *x1, *s, *f0, *f1;  // volumes [z][y][x]
   void *pN, *pT;                // CGLS direction: padded native / transposed copies
   void* t2;                     // second framelet scratch (two levels only)
+  float* tvg;                   // TV: gradient of the ROF energy (FP32 volume)
+  void* rof_state;              // TV: descent state
   size_t pN_elems, pT_elems;
   void *g, *r, *rl, *q;         // projections
   double* partials;
@@ -225,7 +237,10 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
     b.pN = cv.take(b.pN_elems * es);
     b.pT = cv.take(b.pT_elems * es);
     b.s = cv.take(V);
-    b.t2 = o.framelet_levels == 2 ? cv.take(V) : nullptr;
+    b.t2 = (o.framelet_levels == 2 && o.regulariser == 0) ? cv.take(V) : nullptr;
+    b.tvg = o.regulariser == 1 ? static_cast<float*>(cv.take(nvox(cur) * sizeof(float)))
+                               : nullptr;
+    b.rof_state = o.regulariser == 1 ? cv.take(rof_state_bytes()) : nullptr;
     b.f0 = cv.take(V);
     b.f1 = cv.take(V);
     b.g = cv.take(S);
@@ -233,6 +248,8 @@ void make_plan(const tfcb_geometry& g, const tfcb_options& o, void* ws, Plan& P)
     b.rl = cv.take(S);
     b.q = cv.take(S);
     b.max_partials = std::max(project_num_blocks(b.gd), backproject_num_blocks(b.gd));
+    if (o.regulariser == 1)
+      b.max_partials = std::max(b.max_partials, rof_num_partials(cur.nx, cur.ny, cur.nz));
     b.partials = static_cast<double*>(cv.take(sizeof(double) * b.max_partials));
   }
   P.bytes = cv.off;
@@ -413,6 +430,7 @@ tfcb_status reconstruct_t(const tfcb_geometry& g, const tfcb_options& o, const f
 
   Profiler prof;
   prof.s = s;
+  int rof_steps = 0;
   T* cur = nullptr;  // f_cur of the previous (coarser) grid
   for (int l = ng - 1; l >= 0; --l) {
     const GridBufs& b = P.grid[l];
@@ -433,6 +451,20 @@ tfcb_status reconstruct_t(const tfcb_geometry& g, const tfcb_options& o, const f
     const std::vector<double> mom = momentum_schedule(K, o.momentum != 0);
     for (int k = 0; k < K; ++k) {
       Profiler* pf = (o.profile && l == 0) ? &prof : nullptr;
+      if (o.regulariser == 1) {
+        // the TV method (section 2.3): x = CGLS(f) from v = f, f = H(ROF(x))
+        if (k > 0) TFCB_HIP(launch_copy(V, (const T*)f_cur, xa, s));
+        TFCB_TRY(run_cgls<T>(b, P.sc, xa, static_cast<const T*>(b.g), o.cgls_steps, s, pf));
+        int steps = 0;
+        if (pf) TFCB_HIP(pf->mark(2));
+        TFCB_HIP(launch_rof<T>(gg.nx, gg.ny, gg.nz, (float)o.lambda, (float)o.tv_eps, o.tv_tol,
+                               o.tv_max_steps, o.positivity, (const T*)xa, f_nxt, b.tvg,
+                               b.rof_state, b.partials, &steps, s));
+        if (pf) TFCB_HIP(pf->mark(2));
+        rof_steps += steps;
+        std::swap(f_cur, f_nxt);
+        continue;
+      }
       TFCB_TRY(run_cgls<T>(b, P.sc, xa, static_cast<const T*>(b.g), o.cgls_steps, s, pf));
       TFCB_TRY(run_framelet<T>(gg, o.framelet_levels, (float)o.lambda, o.positivity, xa, f_nxt,
                                f_cur, xb, (float)mom[k + 1], static_cast<T*>(b.s),
@@ -462,6 +494,7 @@ tfcb_status reconstruct_t(const tfcb_geometry& g, const tfcb_options& o, const f
     }
     rep->resid2_last = sc_host.resid2;
     rep->cgls_breakdowns = sc_host.breakdowns;
+    rep->rof_steps = rof_steps;
     if (o.profile) {
       TFCB_HIP(prof.totals(rep->kernel_ms, rep->kernel_launches));
       rep->kernel_ms[3] =

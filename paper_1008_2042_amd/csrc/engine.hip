@@ -187,6 +187,87 @@ tfcb_status tfcb_framelet_shrink(int32_t nx, int32_t ny, int32_t nz, int32_t lev
   });
 }
 
+static size_t fdk_ws_bytes(const tfcb_geometry& g) {
+  Carver cv(nullptr);
+  cv.take(sizeof(ViewInfo) * g.n_views);
+  cv.take(sizeof(ColInfo) * (size_t)g.n_views * g.nu);
+  cv.take(sizeof(float) * npix(g));
+  return cv.off;
+}
+
+tfcb_status tfcb_fdk_workspace_size(const tfcb_geometry* g, size_t* bytes) {
+  TFCB_TRY(validate_geometry(g));
+  if (!bytes) return fail(TFCB_EINVAL, "bytes is NULL");
+  *bytes = fdk_ws_bytes(*g);
+  return TFCB_OK;
+}
+
+tfcb_status tfcb_fdk(const tfcb_geometry* g, tfcb_dtype dt, const void* proj, void* vol, void* ws,
+                     size_t ws_bytes, void* stream) {
+  TFCB_TRY(validate_geometry(g));
+  TFCB_TRY(validate_dtype(dt));
+  if (g->angles)
+    return fail(TFCB_EUNSUPPORTED, "FDK needs an equally spaced full orbit (angles = NULL)");
+  if (!fdk_supported(g->nu)) return fail(TFCB_EUNSUPPORTED, "FDK needs nu <= 8192");
+  TFCB_TRY(check_ptr(proj, "proj", dtype_size(dt)));
+  TFCB_TRY(check_ptr(vol, "vol", dtype_size(dt)));
+  TFCB_TRY(check_ws(ws, ws_bytes, fdk_ws_bytes(*g)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(dt, [&](auto tag) -> tfcb_status {
+    using T = decltype(tag);
+    Carver cv(ws);
+    ViewInfo* views = static_cast<ViewInfo*>(cv.take(sizeof(ViewInfo) * g->n_views));
+    ColInfo* cols = static_cast<ColInfo*>(cv.take(sizeof(ColInfo) * (size_t)g->n_views * g->nu));
+    float* q = static_cast<float*>(cv.take(sizeof(float) * npix(*g)));
+    TFCB_HIP(launch_geom_tables(*g, views, cols, s));
+    TFCB_HIP(launch_fdk(make_geom_dev(*g), views, static_cast<const T*>(proj), q,
+                        static_cast<T*>(vol), s));
+    return TFCB_OK;
+  });
+}
+
+tfcb_status tfcb_rof_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(TFCB_EINVAL, "sizes must be >= 1");
+  if ((double)nx * ny * nz >= 2147483647.0) return fail(TFCB_EUNSUPPORTED, "volume too large");
+  if (!bytes) return fail(TFCB_EINVAL, "bytes is NULL");
+  Carver cv(nullptr);
+  cv.take((size_t)nx * ny * nz * sizeof(float));
+  cv.take(rof_state_bytes());
+  cv.take(sizeof(double) * rof_num_partials(nx, ny, nz));
+  *bytes = cv.off;
+  return TFCB_OK;
+}
+
+tfcb_status tfcb_rof(int32_t nx, int32_t ny, int32_t nz, double mu, double eps, double tol,
+                     int32_t max_steps, int32_t positivity, tfcb_dtype dt, const void* x,
+                     void* out, void* ws, size_t ws_bytes, void* stream, int32_t* steps) {
+  size_t need = 0;
+  TFCB_TRY(tfcb_rof_workspace_size(nx, ny, nz, &need));
+  TFCB_TRY(validate_dtype(dt));
+  if (!std::isfinite(mu) || mu < 0.0) return fail(TFCB_EINVAL, "mu must be finite and >= 0");
+  if (!std::isfinite(eps) || !(eps > 0.0)) return fail(TFCB_EINVAL, "eps must be finite and > 0");
+  if (!std::isfinite(tol) || tol < 0.0) return fail(TFCB_EINVAL, "tol must be finite and >= 0");
+  if (max_steps < 0 || max_steps > 100000) return fail(TFCB_EINVAL, "max_steps must be 0..100000");
+  TFCB_TRY(check_ptr(x, "x", dtype_size(dt)));
+  TFCB_TRY(check_ptr(out, "out", dtype_size(dt)));
+  if (x == out) return fail(TFCB_EINVAL, "x and out must not alias");
+  TFCB_TRY(check_ws(ws, ws_bytes, need));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(dt, [&](auto tag) -> tfcb_status {
+    using T = decltype(tag);
+    Carver cv(ws);
+    float* g = static_cast<float*>(cv.take((size_t)nx * ny * nz * sizeof(float)));
+    void* state = cv.take(rof_state_bytes());
+    double* partials = static_cast<double*>(cv.take(sizeof(double) * rof_num_partials(nx, ny, nz)));
+    int n = 0;
+    TFCB_HIP(launch_rof<T>(nx, ny, nz, (float)mu, (float)eps, tol, max_steps, positivity ? 1 : 0,
+                           static_cast<const T*>(x), static_cast<T*>(out), g, state, partials, &n,
+                           s));
+    if (steps) *steps = n;
+    return TFCB_OK;
+  });
+}
+
 tfcb_status tfcb_cgls(const tfcb_geometry* g, const tfcb_options* o, void* x, const void* proj,
                       void* ws, size_t ws_bytes, void* stream, double* stats) {
   TFCB_TRY(validate_geometry(g));

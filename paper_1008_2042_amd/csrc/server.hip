@@ -290,6 +290,8 @@ tfcb_status tfcb_server_submit(tfcb_server* S, const tfcb_geometry* g, const tfc
   TFCB_TRY(validate_geometry(g));
   TFCB_TRY(validate_options(o));
   TFCB_TRY(validate_schedule(*g, *o));
+  if (o->regulariser != 0)
+    return fail(TFCB_EUNSUPPORTED, "the server runs the tight-frame method only (regulariser 0)");
   TFCB_TRY(check_ptr(proj, "proj", sizeof(float)));
   TFCB_TRY(check_ptr(vol, "vol", sizeof(float)));
   std::unique_ptr<Request> R(new Request());

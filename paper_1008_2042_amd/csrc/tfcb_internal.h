@@ -251,6 +251,27 @@ hipError_t launch_cast(size_t n, const Tin* in, Tout* out, hipStream_t s);
 template <typename T>
 hipError_t launch_nonfinite(size_t n, const T* in, int* flag, hipStream_t s);
 
+// The ROF sub-problem of the TV comparison method (section 2.3): f from
+// x by gradient descent with an adaptive step (see tv.hip), then H when
+// positivity is set.  g: float volume scratch; state: rof_state_bytes();
+// partials: rof_num_partials() doubles.  Synchronises `s` between chunks
+// of attempts to read the stop flag; *steps_host = accepted steps.
+template <typename T>
+hipError_t launch_rof(int nx, int ny, int nz, float mu, float eps, double tol, int max_steps,
+                      int positivity, const T* x, T* f, float* g, void* state, double* partials,
+                      int* steps_host, hipStream_t s);
+int rof_num_partials(int nx, int ny, int nz);
+size_t rof_state_bytes();
+
+// FDK (the comparison baseline): q = cosine-weighted, Ram-Lak-filtered
+// projections (FP32 scratch, n_views * nv * nu), then the weighted
+// backprojection into vol.  Needs nu <= 8192 (fdk_supported) and equally
+// spaced views (the tables of views hold their angles).
+template <typename T>
+hipError_t launch_fdk(const GeomDev& g, const ViewInfo* views, const T* proj, float* q, T* vol,
+                      hipStream_t s);
+bool fdk_supported(int nu);
+
 // Multigrid.
 template <typename T>
 hipError_t launch_restrict(int n_views, int nu, int nv, const T* in, T* out, hipStream_t s);

@@ -25,7 +25,8 @@ EXPORTS = [
     "tfcb_workspace_size", "tfcb_operator_workspace_size", "tfcb_framelet_workspace_size",
     "tfcb_project", "tfcb_backproject", "tfcb_backproject_noalloc", "tfcb_project_siddon",
     "tfcb_backproject_eq3",
-    "tfcb_framelet_shrink", "tfcb_cgls",
+    "tfcb_framelet_shrink", "tfcb_rof_workspace_size", "tfcb_rof", "tfcb_cgls",
+    "tfcb_fdk_workspace_size", "tfcb_fdk",
     "tfcb_restrict_sino", "tfcb_prolong_vol", "tfcb_reconstruct",
     "tfcb_request_bytes", "tfcb_server_create", "tfcb_server_submit", "tfcb_server_step",
     "tfcb_server_poll", "tfcb_server_cancel", "tfcb_server_destroy",
@@ -54,14 +55,16 @@ class Options(ctypes.Structure):
                 ("framelet_levels", ctypes.c_int32), ("momentum", ctypes.c_int32),
                 ("positivity", ctypes.c_int32), ("bin_coarse_detector", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("op_pair", ctypes.c_int32)]
+                ("op_pair", ctypes.c_int32), ("regulariser", ctypes.c_int32),
+                ("tv_eps", ctypes.c_double), ("tv_tol", ctypes.c_double),
+                ("tv_max_steps", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("seconds_total", ctypes.c_double), ("seconds_per_grid", ctypes.c_double * 4),
                 ("iters_done", ctypes.c_int32 * 4), ("resid2_last", ctypes.c_double),
                 ("cgls_breakdowns", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 4),
-                ("kernel_launches", ctypes.c_int32 * 4)]
+                ("kernel_launches", ctypes.c_int32 * 4), ("rof_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -93,6 +96,11 @@ def load(path: str = LIB_PATH):
         "tfcb_project_siddon": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_backproject_eq3": ([G, i32, vp, vp, vp, sz, vp], i32),
         "tfcb_framelet_shrink": ([i32, i32, i32, i32, dbl, i32, i32, vp, vp, vp, sz, vp], i32),
+        "tfcb_fdk_workspace_size": ([G, psz], i32),
+        "tfcb_fdk": ([G, i32, vp, vp, vp, sz, vp], i32),
+        "tfcb_rof_workspace_size": ([i32, i32, i32, psz], i32),
+        "tfcb_rof": ([i32, i32, i32, dbl, dbl, dbl, i32, i32, i32, vp, vp, vp, sz, vp,
+                      ctypes.POINTER(i32)], i32),
         "tfcb_cgls": ([G, O, vp, vp, vp, sz, vp, ctypes.POINTER(dbl)], i32),
         "tfcb_restrict_sino": ([G, i32, vp, vp, vp], i32),
         "tfcb_prolong_vol": ([G, G, i32, vp, vp, vp], i32),
@@ -133,13 +141,21 @@ def geometry(g) -> Geometry:
     return s
 
 
+TV_EPS, TV_TOL, TV_MAX_STEPS = 1e-5, 1e-3, 100
+
+
 def options(lam: float, iters: Sequence[int], cgls_steps: int = 3, framelet_levels: int = 1,
             momentum: bool = True, positivity: bool = True, bin_detector: bool = True,
-            storage: int = F32, profile: bool = False, op_pair: int = 0) -> Options:
+            storage: int = F32, profile: bool = False, op_pair: int = 0, regulariser: int = 0,
+            tv_eps: float = TV_EPS, tv_tol: float = TV_TOL,
+            tv_max_steps: int = TV_MAX_STEPS) -> Options:
+    """regulariser 0: the tight-frame method (lam = the shrink threshold);
+    1: the TV comparison method (lam = mu_TV)."""
     it = list(iters) + [0] * (4 - len(iters))
     return Options(float(lam), len(iters), (ctypes.c_int32 * 4)(*it), int(cgls_steps),
                    int(framelet_levels), int(bool(momentum)), int(bool(positivity)),
-                   int(bool(bin_detector)), int(storage), int(bool(profile)), int(op_pair))
+                   int(bool(bin_detector)), int(storage), int(bool(profile)), int(op_pair),
+                   int(regulariser), float(tv_eps), float(tv_tol), int(tv_max_steps))
 
 
 # ---------------------------------------------------------------- torch side
@@ -276,6 +292,41 @@ def framelet_shrink(vol, lam: float, levels: int = 1, positivity: bool = True, o
     return out
 
 
+def fdk(g, proj, out=None, stream=None):
+    """FDK reconstruction (the comparison baseline) of device projections."""
+    torch = _torch()
+    dt = dtype_code(proj.dtype)
+    if out is None:
+        out = torch.empty((g.nz, g.ny, g.nx), dtype=proj.dtype, device=proj.device)
+    n = ctypes.c_size_t(0)
+    lib = load()
+    _check(lib.tfcb_fdk_workspace_size(ctypes.byref(geometry(g)), ctypes.byref(n)))
+    ws = _workspace(n.value, proj.device)
+    _check(lib.tfcb_fdk(ctypes.byref(geometry(g)), dt, _ptr(proj), _ptr(out), _ptr(ws),
+                        ws.numel(), _stream(stream)))
+    return out
+
+
+def rof(x, mu: float, eps: float = TV_EPS, tol: float = TV_TOL, max_steps: int = TV_MAX_STEPS,
+        positivity: bool = False, out=None, stream=None):
+    """The ROF sub-problem of the TV method by the library's gradient descent
+    (synchronises the stream).  Returns (out, accepted steps)."""
+    torch = _torch()
+    nz, ny, nx = x.shape
+    dt = dtype_code(x.dtype)
+    if out is None:
+        out = torch.empty_like(x)
+    n = ctypes.c_size_t(0)
+    lib = load()
+    _check(lib.tfcb_rof_workspace_size(nx, ny, nz, ctypes.byref(n)))
+    ws = _workspace(n.value, x.device)
+    steps = ctypes.c_int32(0)
+    _check(lib.tfcb_rof(nx, ny, nz, float(mu), float(eps), float(tol), int(max_steps),
+                        int(bool(positivity)), dt, _ptr(x), _ptr(out), _ptr(ws), ws.numel(),
+                        _stream(stream), ctypes.byref(steps)))
+    return out, int(steps.value)
+
+
 def cgls(g, x, proj, n: int, stream=None, op_pair: int = 0):
     """n CGLS steps from x (updated in place), with the Joseph pair or
     (op_pair 1) the paper's Siddon / Eq. (3) pair.  Returns (x, resid2, broke)."""
@@ -309,13 +360,16 @@ def prolong_vol(g_coarse, g_fine, vol, stream=None):
 def reconstruct(g, proj, lam: float, iters: Sequence[int], cgls_steps: int = 3,
                 framelet_levels: int = 1, momentum: bool = True, positivity: bool = True,
                 bin_detector: bool = True, storage: int = F32, out=None, ws=None, stream=None,
-                check: bool = True, profile: bool = False, op_pair: int = 0):
+                check: bool = True, profile: bool = False, op_pair: int = 0,
+                regulariser: int = 0, tv_eps: float = TV_EPS, tv_tol: float = TV_TOL,
+                tv_max_steps: int = TV_MAX_STEPS):
     """The full method on device FP32 projections; returns (volume, report dict).
-    op_pair 1 runs the CGLS with the paper's Siddon / Eq. (3) operators.
+    op_pair 1 runs the CGLS with the paper's Siddon / Eq. (3) operators;
+    regulariser 1 runs the TV comparison method with lam as mu_TV.
     The call synchronises the stream."""
     torch = _torch()
     opts = options(lam, iters, cgls_steps, framelet_levels, momentum, positivity, bin_detector,
-                   storage, profile, op_pair)
+                   storage, profile, op_pair, regulariser, tv_eps, tv_tol, tv_max_steps)
     if out is None:
         out = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=proj.device)
     need = workspace_size(g, opts)
@@ -331,7 +385,8 @@ def reconstruct(g, proj, lam: float, iters: Sequence[int], cgls_steps: int = 3,
               "seconds_per_grid": list(rep.seconds_per_grid)[:len(iters)],
               "iters_done": list(rep.iters_done)[:len(iters)], "resid2_last": rep.resid2_last,
               "cgls_breakdowns": rep.cgls_breakdowns,
-              "kernel_ms": list(rep.kernel_ms), "kernel_launches": list(rep.kernel_launches)}
+              "kernel_ms": list(rep.kernel_ms), "kernel_launches": list(rep.kernel_launches),
+              "rof_steps": rep.rof_steps}
     return out, report
 
 

@@ -152,3 +152,29 @@ def test_every_grid_of_the_schedule_is_validated():
     assert lib.tfcb_workspace_size(ctypes.byref(tfcb.geometry(wide)), ctypes.byref(o3),
                                    ctypes.byref(n)) == tfcb.EINVAL
     assert b"coarse grid 2" in lib.tfcb_last_error()
+
+
+def test_tv_options_and_rof_arguments_checked():
+    lib = _lib()
+    g = tfcb.geometry(inputs.config("tiny")["geom"])
+    n = ctypes.c_size_t(0)
+    ok = tfcb.options(5e-4, [10], regulariser=1)
+    assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(ok), ctypes.byref(n)) == 0
+    tf = ctypes.c_size_t(0)
+    assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(tfcb.options(5e-4, [10])),
+                                   ctypes.byref(tf)) == 0
+    assert n.value > tf.value  # the FP32 gradient volume and descent state
+    for kw in (dict(regulariser=2), dict(regulariser=1, tv_eps=0.0),
+               dict(regulariser=1, tv_tol=-1.0), dict(regulariser=1, tv_max_steps=-1)):
+        o = tfcb.options(5e-4, [10], **kw)
+        assert lib.tfcb_workspace_size(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) \
+            == tfcb.EINVAL, kw
+    assert lib.tfcb_rof_workspace_size(8, 8, 8, ctypes.byref(n)) == 0 and n.value >= 8 ** 3 * 4
+    nul = ctypes.c_int32(0)
+    args = (8, 8, 8, 1e-3, 1e-5, 1e-3, 100, 1, 0)
+    assert lib.tfcb_rof(*args, 256, 256, 256, n.value, None, ctypes.byref(nul)) == tfcb.EINVAL
+    assert lib.tfcb_rof(*args, None, 512, 256, n.value, None, ctypes.byref(nul)) == tfcb.EINVAL
+    assert lib.tfcb_rof(8, 8, 8, -1.0, 1e-5, 1e-3, 100, 1, 0, 256, 512, 256, n.value, None,
+                        ctypes.byref(nul)) == tfcb.EINVAL
+    assert lib.tfcb_rof(*args, 256, 512, 256, n.value - 1, None, ctypes.byref(nul)) \
+        == tfcb.ENOMEM

@@ -50,8 +50,10 @@ def test_large_project_sampled_and_adjoint():
     pty = tfcb.backproject(g, y)
     lhs = float(torch.sum(pf.double() * y.double()))
     rhs = float(torch.sum(fd.double() * pty.double()))
-    err = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
-    print("large adjoint identity: relative mismatch %.2e" % err, flush=True)
+    scale = float(torch.linalg.norm(pf.double()) * torch.linalg.norm(y.double()))
+    err = abs(lhs - rhs) / scale
+    print("large adjoint identity: mismatch %.2e of ||Pf|| ||y||, %.2e of <Pf, y>"
+          % (err, abs(lhs - rhs) / abs(lhs)), flush=True)
     assert err <= 1e-6
 
 

@@ -96,6 +96,19 @@ def test_too_large_request_rejected():
     srv.close()
 
 
+def test_tv_request_refused():
+    """The server runs the tight-frame method only; a TV request is refused
+    at submission."""
+    dev = _dev()
+    r = _requests(dev)[0]
+    srv = tfcb.Server(r["bytes"] * 2, 2)
+    o = tfcb.options(5e-4, [2], storage=tfcb.F16, regulariser=1)
+    with pytest.raises(tfcb.TfcbError) as ei:
+        srv.submit(r["geom"], r["proj"], o)
+    assert ei.value.status == tfcb.EUNSUPPORTED
+    srv.close()
+
+
 def test_nan_request_fails_alone():
     dev = _dev()
     reqs = _requests(dev)[:3]
