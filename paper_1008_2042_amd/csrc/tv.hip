@@ -196,6 +196,21 @@ __global__ __launch_bounds__(256) void k_nonneg(size_t n, T* __restrict__ f) {
 
 static dim3 tv_grid(int nx, int ny, int nz) { return dim3((nx + 63) / 64, (ny + 3) / 4, nz); }
 
+// Two pinned host copies of the descent state per host thread (the stop
+// flag read back between chunks), allocated on first use and kept for the
+// life of the process.
+static hipError_t rof_pinned_state(RofState** out) {
+  static thread_local RofState* pinned = nullptr;
+  if (!pinned) {
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, 2 * sizeof(RofState), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    pinned = static_cast<RofState*>(p);
+  }
+  *out = pinned;
+  return hipSuccess;
+}
+
 int rof_num_partials(int nx, int ny, int nz) {
   const dim3 gr = tv_grid(nx, ny, nz);
   return (int)(gr.x * gr.y * gr.z);
@@ -238,19 +253,42 @@ hipError_t launch_rof(int nx, int ny, int nz, float mu, float eps, double tol, i
   hipLaunchKernelGGL(k_tv_decide, dim3(1), dim3(kReduceThreads), 0, s, (const double*)partials,
                      np, tol, max_steps, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // attempts in chunks; between chunks the host reads the stop flag
+  // Attempts in chunks, two chunks in flight: after enqueueing chunk c the
+  // host waits for chunk c - 1 and reads the state it copied to pinned host
+  // memory, so the device never idles on the host's decision; the chunk
+  // enqueued past the stop only runs kernels that return at once.
   constexpr int kChunk = 4;
   const int max_attempts = max_steps * 42 + 1;  // each step: at most 41 trials
+  RofState* pinned = nullptr;
+  if ((e = rof_pinned_state(&pinned)) != hipSuccess) return e;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (int b = 0; b < 2; ++b)
+    if ((e = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming)) != hipSuccess) return e;
+  int last = -1;
   RofState host{};
-  for (int a = 0; a < max_attempts; a += kChunk) {
-    for (int c = 0; c < kChunk; ++c)
+  for (int c = 0; c * kChunk < max_attempts; ++c) {
+    for (int a = 0; a < kChunk; ++a)
       if ((e = rof_attempt<T>(p, x, f, g, st, partials, tol, max_steps, s)) != hipSuccess)
-        return e;
-    if ((e = hipMemcpyAsync(&host, st, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (host.stopped) break;
+        break;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&pinned[c & 1], st, sizeof(RofState), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[c & 1], s);
+    if (e != hipSuccess) break;
+    last = c;
+    if (c > 0) {
+      if ((e = hipEventSynchronize(ev[(c - 1) & 1])) != hipSuccess) break;
+      host = pinned[(c - 1) & 1];
+      if (host.stopped) break;
+    }
   }
+  // the newest chunk's copy is still in flight: wait for it before the
+  // pinned words are reused
+  if (e == hipSuccess && last >= 0) {
+    e = hipEventSynchronize(ev[last & 1]);
+    if (e == hipSuccess) host = pinned[last & 1];
+  }
+  for (int b = 0; b < 2; ++b) (void)hipEventDestroy(ev[b]);
+  if (e != hipSuccess) return e;
   if (steps_host) *steps_host = host.steps;
   if (positivity) {
     hipLaunchKernelGGL((k_nonneg<T>), dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, V, f);
