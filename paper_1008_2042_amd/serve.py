@@ -113,3 +113,27 @@ def serving_benchmark(n: int = 64, seed: int = 404, load: float = 0.8,
                                "two largest order statistics" % n)
     out.update({k: round(v, 4) for k, v in percentiles(run["latency"]).items()})
     return out
+
+
+def main():
+    """Closed-loop capacity of a seeded mix (every request submitted at
+    time 0), for kernel traces of the serving path:
+        python -m paper_1008_2042_amd.serve --requests 64 --slots 3"""
+    import argparse
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=3)
+    ap.add_argument("--arena-gb", type=float, default=8.0)
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    reqs = build_requests(inputs.serving_mix(args.requests, 404), dev, tfcb.F16)
+    torch.cuda.synchronize()
+    sat = replay(reqs, np.zeros(args.requests), int(args.arena_gb * (1 << 30)), args.slots)
+    print("closed loop: %d requests, %d slots, makespan %.3f s, %.1f reconstructions/min"
+          % (args.requests, args.slots, sat["makespan"], 60 * args.requests / sat["makespan"]),
+          flush=True)
+
+
+if __name__ == "__main__":
+    main()
