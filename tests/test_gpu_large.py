@@ -54,7 +54,7 @@ def test_large_project_sampled_and_adjoint():
     err = abs(lhs - rhs) / scale
     print("large adjoint identity: mismatch %.2e of ||Pf|| ||y||, %.2e of <Pf, y>"
           % (err, abs(lhs - rhs) / abs(lhs)), flush=True)
-    assert err <= 1e-6
+    assert err <= 1e-7
 
 
 @pytest.mark.parametrize("levels", [1, 2])

@@ -131,7 +131,7 @@ def test_adjoint_identity_gpu(g):
     err = abs(lhs - rhs) / (np.linalg.norm(pf) * np.linalg.norm(y))
     print("adjoint identity: mismatch %.2e of ||Pf|| ||y||, %.2e of <Pf, y>"
           % (err, abs(lhs - rhs) / abs(lhs)), flush=True)
-    assert err <= 1e-6
+    assert err <= 1e-7
 
 
 FRAMELET_SHAPES = [(16, 64, 64), (19, 33, 70), (1, 5, 7), (2, 1, 3), (3, 17, 31)]
