@@ -6,10 +6,13 @@
 // solver state on the device (its own workspace inside the arena) and runs
 // on its own stream; every server step enqueues the next outer iteration of
 // every active request, so the work of concurrent requests overlaps on the
-// GPU while new requests are admitted and finished ones retired.  A request
-// runs exactly the kernels and launch shapes of tfcb_reconstruct on its own
-// buffers, with deterministic reductions, so its result is bitwise the same
-// alone or in any mix.
+// GPU while new requests are admitted and finished ones retired.  The CGLS
+// step of an iteration (some 25 launches) is captured as a graph per grid
+// and iterate buffer the first time it runs and replayed after that; the
+// framelet step, whose momentum coefficient changes every iteration, is
+// launched directly.  A request runs exactly the kernels and launch shapes
+// of tfcb_reconstruct on its own buffers, with deterministic reductions, so
+// its result is bitwise the same alone or in any mix.
 #include <chrono>
 #include <deque>
 #include <map>
@@ -89,6 +92,9 @@ struct Request {
   std::vector<double> mom;
   void *f_cur = nullptr, *f_nxt = nullptr, *xa = nullptr, *xb = nullptr;
   bool enqueued_all = false;
+  // the CGLS step of one outer iteration per grid and x buffer (x0 or x1 as
+  // the iterate), captured on first use and replayed after that
+  hipGraphExec_t cgls_graph[4][2] = {};
   hipEvent_t done_ev = nullptr;
   std::deque<hipEvent_t> inflight;
   double t_done = 0.0;
@@ -185,6 +191,35 @@ tfcb_status finish(tfcb_server* S, Request& R) {
   return TFCB_OK;
 }
 
+// The CGLS step of R's current outer iteration.  Its launches depend only on
+// the grid and on which x buffer holds the iterate, so each such pair is
+// captured once as a graph (no memset nodes: every fill is a kernel) and
+// replayed on every later iteration.
+template <typename T>
+tfcb_status cgls_step(tfcb_server* S, Request& R, const GridBufs& b, hipStream_t s) {
+  hipGraphExec_t& exec = R.cgls_graph[R.grid][R.xa == b.x0 ? 0 : 1];
+  if (!exec) {
+    TFCB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const tfcb_status st = run_cgls<T>(b, R.plan.sc, static_cast<T*>(R.xa),
+                                       static_cast<const T*>(b.g), R.opts.cgls_steps, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != TFCB_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    TFCB_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      exec = nullptr;
+      return fail(TFCB_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    }
+  }
+  TFCB_HIP(hipGraphLaunch(exec, s));
+  return TFCB_OK;
+}
+
 // Enqueues the next outer iteration of R (and any grid transition).
 template <typename T>
 tfcb_status advance(tfcb_server* S, Request& R) {
@@ -200,8 +235,7 @@ tfcb_status advance(tfcb_server* S, Request& R) {
     TFCB_TRY(start_grid<T>(S, R, R.grid - 1));
   }
   const GridBufs& b = R.plan.grid[R.grid];
-  TFCB_TRY(run_cgls<T>(b, R.plan.sc, static_cast<T*>(R.xa), static_cast<const T*>(b.g),
-                       R.opts.cgls_steps, s));
+  TFCB_TRY(cgls_step<T>(S, R, b, s));
   TFCB_TRY(run_framelet<T>(b.geom, R.opts.framelet_levels, (float)R.opts.lambda,
                            R.opts.positivity, static_cast<const T*>(R.xa),
                            static_cast<T*>(R.f_nxt), static_cast<const T*>(R.f_cur),
@@ -225,6 +259,12 @@ tfcb_status advance_any(tfcb_server* S, Request& R) {
 }
 
 void release_request(tfcb_server* S, Request& R) {
+  for (auto& per_grid : R.cgls_graph)
+    for (hipGraphExec_t& e : per_grid)
+      if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
   if (R.ready_ev) {
     S->pool.push_back(R.ready_ev);
     R.ready_ev = nullptr;
