@@ -203,8 +203,10 @@ def kernel_fractions(g, avg_ms, samples):
     """Per kernel of the fine grid: the HBM fraction of its compulsory bytes
     (P: volume + projections; P^T: the same; framelet: 16 B per voxel in
     FP32), the HBM-side traffic rate from the committed counters, and the
-    VALU issue fraction (SQ_INSTS_VALU per launch over one wave instruction
-    per clock per CU at 2.4 GHz, the rate of non-packed FP32 code)."""
+    VALU instruction rate per CU and 2.4 GHz clock (SQ_INSTS_VALU per launch
+    over 256 CUs x 2.4e9 x the launch's duration).  Non-packed FP32 code
+    issues about one wave instruction per CU-clock, but the counter is a
+    rate, not a bound: the 512x512x256 projector measures 1.13."""
     V, S = g.nx * g.ny * g.nz * 4.0, g.n_views * g.nu * g.nv * 4.0
     compulsory = [V + S, V + S, 16.0 * g.nx * g.ny * g.nz]
     out = {}
@@ -221,7 +223,7 @@ def kernel_fractions(g, avg_ms, samples):
             d["traffic_frac_of_8TBps"] = round(ent["bytes_per_launch"] / t / 8e12, 4)
         if ent.get("valu_insts_per_launch"):
             d["valu_insts_per_launch"] = ent["valu_insts_per_launch"]
-            d["valu_issue_frac"] = round(ent["valu_insts_per_launch"] / t / (256 * 2.4e9), 4)
+            d["valu_insts_per_cu_clock"] = round(ent["valu_insts_per_launch"] / t / (256 * 2.4e9), 4)
             if i == 0:
                 d["lane_valu_per_sample"] = round(64.0 * ent["valu_insts_per_launch"] / samples, 2)
         out[name] = d
