@@ -14,6 +14,7 @@
 // around it.  RPT = 1 (NL = 2) is the one-ray-per-thread kernel.  PU planes
 // per iteration, alternating between two accumulator sets.
 #include <cmath>
+#include <type_traits>
 
 #include "tfcb_internal.h"
 
@@ -26,6 +27,19 @@ __device__ __forceinline__ float trans_index(const ColInfo& ci, int p) {
 }
 __device__ __forceinline__ float z_index(const ColInfo& ci, int p, float vz, float zc) {
   return fmaf(fmaf((float)p, ci.dtau, ci.tau0), vz, zc);
+}
+// floor(x) as an int in one conversion (v_cvt_flr_i32_f32), |x| < 2^31
+__device__ __forceinline__ int floor_int(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+// x clamped to [LO, hi] in one instruction (LO a small constant, hi uniform)
+template <int LO>
+__device__ __forceinline__ int clamp_int(int x, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "n"(LO), "s"(hi));
+  return r;
 }
 __device__ __forceinline__ bool sample_inside(const ColInfo& ci, int p, float vz, float zc,
                                               int nt, int nz) {
@@ -296,12 +310,12 @@ __device__ __forceinline__ void sample_rows_lds(const float* __restrict__ tile, 
                                                 float zc, int nt, int nz, float (&acc)[RPT]) {
   const float th = trans_index(ci, p);
   const float tf = floorf(th);
-  const int it = min(max((int)tf, -1), nt - 1);
+  const int it = clamp_int<-1>((int)tf, nt - 1);
   const float wt = th - tf;
   float fr[RPT];  // z fractions, v_fract (the hardware's x - floor(x))
 #pragma unroll
   for (int j = 0; j < RPT; ++j) fr[j] = __builtin_amdgcn_fractf(z_index(ci, p, vz[j], zc));
-  const int iz0 = min(max((int)floorf(z_index(ci, p, vz[0], zc)), -kZPad), nz - 1);
+  const int iz0 = clamp_int<-kZPad>(floor_int(z_index(ci, p, vz[0], zc)), nz - 1);
   const float* __restrict__ q = tile + (iz0 - b.zl) * (4 * kStageF4) + (it - b.tl4);
   float lev[NL];
 #pragma unroll
@@ -355,9 +369,10 @@ __device__ __forceinline__ bool map_block(const BlockMap& m, int& bx, int& by, i
 }
 
 template <typename T, int MODE, int RPT, int NL>
-// Plans of at most 8 rows fit 128 VGPRs: four waves per SIMD (and four blocks
-// per CU within LDS).
-__global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev g, BlockMap bm, const ViewInfo* __restrict__ views,
+// Every plan fits 128 VGPRs (the rows' z factors, uniform over a wave, sit in
+// scalar registers): at least four waves per SIMD, four blocks per CU within
+// LDS.
+__global__ __launch_bounds__(256, 4) void k_project_staged(GeomDev g, BlockMap bm, const ViewInfo* __restrict__ views,
                                                         const ColInfo* __restrict__ cols,
                                                         const T* __restrict__ padN,
                                                         const T* __restrict__ padT,
@@ -368,10 +383,16 @@ __global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev
   __shared__ double red[4];
   __shared__ int srange[8];
   __shared__ float4 tile[2][kStageRows * kStageF4];
-  __shared__ int4 boxes[kStageBoxes];
+  // the box table: packed into two ints per plane where the box is moved to
+  // scalar registers (plans of at most 8 rows: (zl << 8 | nzr, tl4 << 8 |
+  // nf4), the counts being at most kStageRows and kStageF4 on every plane
+  // of a staged block), four ints otherwise
+  constexpr bool kScalarBox = RPT <= 8;
+  static_assert(kStageRows < 256 && kStageF4 < 256, "box counts packed in 8 bits");
+  __shared__ std::conditional_t<kScalarBox, int2, int4> boxes[kStageBoxes];
   int bx, by, bz;
   if (!map_block(bm, bx, by, bz)) return;  // the whole block: before any barrier
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cblk = bx * 64, rblk = by * 4 * RPT;
   const int c = cblk + lane;
   const int r0 = rblk + wave * RPT;
@@ -389,7 +410,9 @@ __global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev
   int lo = ns, hi = -1;  // union of the rows' windows
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    vz[j] = ((float)(r0 + j) - 0.5f * (float)(g.nv - 1)) * g.dvdz;
+    // uniform over the wave: kept in a scalar register
+    vz[j] = __int_as_float(__builtin_amdgcn_readfirstlane(
+        __float_as_int(((float)(r0 + j) - 0.5f * (float)(g.nv - 1)) * g.dvdz)));
     if (active && r0 + j < g.nv) {
       int l, h;
       plane_range(ci, vz[j], zc, nt, nz, l, h);
@@ -446,12 +469,34 @@ __global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev
     if (table)
       for (int i = threadIdx.x; i <= HI - LO; i += 256) {
         const StageBox b = stage_box(cA, cB, vzA, vzB, LO + i, zc, nt, nz, NL);
-        boxes[i] = make_int4(b.zl, b.nzr, b.tl4, b.nf4);
+        if constexpr (kScalarBox)
+          boxes[i] = make_int2(b.zl * 256 + b.nzr, b.tl4 * 256 + b.nf4);
+        else
+          boxes[i] = make_int4(b.zl, b.nzr, b.tl4, b.nf4);
       }
     __syncthreads();
     auto get_box = [&](int p) {
       StageBox b;
-      if (table) {
+      if constexpr (kScalarBox) {
+        // the same for every thread: moved to scalar registers, so that
+        // the staging addresses are computed on the scalar unit
+        int x, y;
+        if (table) {
+          const int2 v = boxes[p - LO];
+          x = v.x;
+          y = v.y;
+        } else {
+          const StageBox c = stage_box(cA, cB, vzA, vzB, p, zc, nt, nz, NL);
+          x = c.zl * 256 + c.nzr;
+          y = c.tl4 * 256 + c.nf4;
+        }
+        x = __builtin_amdgcn_readfirstlane(x);
+        y = __builtin_amdgcn_readfirstlane(y);
+        b.zl = x >> 8;
+        b.nzr = x & 0xff;
+        b.tl4 = y >> 8;
+        b.nf4 = y & 0xff;
+      } else if (table) {
         const int4 v = boxes[p - LO];
         b.zl = v.x;
         b.nzr = v.y;
@@ -489,8 +534,14 @@ __global__ __launch_bounds__(256, RPT > 8 ? 1 : 4) void k_project_staged(GeomDev
       // bounds; the samples read only inside the box), so no load is
       // conditional
 #pragma unroll
-      for (int k = 0; k < kStageRegs; ++k)
-        r[k] = ld_raw4(first + ((srow[k] < b.nzr && sq4[k] < b.nf4) ? soff[k] : 0));
+      for (int k = 0; k < kStageRegs; ++k) {
+        const bool in = srow[k] < b.nzr && sq4[k] < b.nf4;
+        if constexpr (kScalarBox)  // a 32-bit byte offset from the scalar first element
+          r[k] = ld_raw4(reinterpret_cast<const T*>(reinterpret_cast<const char*>(first) +
+                                                    (in ? (unsigned)soff[k] * sizeof(T) : 0u)));
+        else
+          r[k] = ld_raw4(first + (in ? soff[k] : 0));
+      }
     };
     auto stage_store = [&](const Raw (&r)[kStageRegs], int buf) {
 #pragma unroll
