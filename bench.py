@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 METRIC = "TF iterations/s + s/recon at 512²×70 (FP32 vs FP16-store); serving p99 latency"
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X: 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
 FLOPS_PER_SAMPLE = 16.0          # algorithmic work of one (ray, plane) sample
+VL1D_BYTES_PER_CLK_CU = 64.0     # vector L1 peak per CU and clock (the CDNA3 figure)
 KERNEL_NAMES = ["P (k_project)", "P^T (k_backproject)", "framelet (k_framelet)"]
 KERNEL_SOURCES = ["project.hip", "backproject.hip", "framelet.hip"]
 TV_MU = 5e-4  # mu_TV of the TV comparison run (1/mm), tuned by hand as the paper does
@@ -199,16 +200,42 @@ def load_counters(kernel_idx: int):
     return ent
 
 
-def kernel_fractions(g, avg_ms, samples):
+def copy_bandwidth(dev, nbytes: int = 1 << 30) -> float:
+    """Achieved rate of a plain device copy, read + write bytes per second:
+    a 1 GiB device-to-device tensor copy, median of 5 after one untimed
+    call.  The reference for the compulsory-byte fractions."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2.0 * nbytes / sorted(ts)[2]
+
+
+def kernel_fractions(g, avg_ms, samples, copy_Bps=None):
     """Per kernel of the fine grid: the HBM fraction of its compulsory bytes
     (P: volume + projections; P^T: the same; framelet: 16 B per voxel in
-    FP32), the HBM-side traffic rate from the committed counters, and the
+    FP32), against the 8 TB/s peak and against the measured rate of a plain
+    device copy; for P and P^T the algorithmic tap bytes (4 taps of 4 bytes
+    per sample, the gathers a matrix-free design must make) against the
+    vector L1 peak of 64 B per clock per CU (256 CUs at 2.4 GHz; the kernels
+    here take their taps from LDS, so this is the gather rate they stand in
+    for); the HBM-side traffic rate from the committed counters, and the
     VALU instruction rate per CU and 2.4 GHz clock (SQ_INSTS_VALU per launch
     over 256 CUs x 2.4e9 x the launch's duration).  Non-packed FP32 code
     issues about one wave instruction per CU-clock, but the counter is a
     rate, not a bound: the 512x512x256 projector measures 1.13."""
     V, S = g.nx * g.ny * g.nz * 4.0, g.n_views * g.nu * g.nv * 4.0
     compulsory = [V + S, V + S, 16.0 * g.nx * g.ny * g.nz]
+    vl1d_peak = VL1D_BYTES_PER_CLK_CU * 256 * 2.4e9
     out = {}
     for i, name in enumerate(KERNEL_NAMES):
         t = avg_ms[i] * 1e-3
@@ -217,6 +244,11 @@ def kernel_fractions(g, avg_ms, samples):
         ent = load_counters(i)
         d = {"compulsory_bytes": int(compulsory[i]),
              "hbm_frac_compulsory": round(compulsory[i] / t / 8e12, 4)}
+        if copy_Bps:
+            d["hbm_frac_compulsory_vs_copy"] = round(compulsory[i] / t / copy_Bps, 4)
+        if i in (0, 1):
+            d["tap_bytes"] = int(16 * samples)
+            d["vl1d_frac_tap_bytes"] = round(16.0 * samples / t / vl1d_peak, 4)
         if ent.get("bytes_per_launch"):
             d["traffic_bytes"] = ent["bytes_per_launch"]
             d["traffic_GBps"] = round(ent["bytes_per_launch"] / t / 1e9, 1)
@@ -338,6 +370,7 @@ def main():
     avg_ms = [float(kms[i] / kn[i]) if kn[i] else 0.0 for i in range(3)]
     dom = int(np.argmax(kms[:3]))
     samples = plane_samples(g)
+    copy_Bps = copy_bandwidth(dev)
     roofline = None
     if dom in (0, 1):
         flops = samples * FLOPS_PER_SAMPLE
@@ -369,7 +402,8 @@ def main():
                    "coarse_grid_iters_per_s": round(cfg["iters"][0] / np.mean(
                        [r["seconds_per_grid"][0] for r in reps]), 3),
                    "kernel_avg_ms": {KERNEL_NAMES[i]: round(avg_ms[i], 4) for i in range(3)},
-                   "kernel_fractions": kernel_fractions(g, avg_ms, samples),
+                   "copy_GBps": round(copy_Bps / 1e9, 1),
+                   "kernel_fractions": kernel_fractions(g, avg_ms, samples, copy_Bps),
                    "kernel_share_fine_grid": {
                        n: round(float(kms[i] / max(np.sum(kms), 1e-30)), 3)
                        for i, n in enumerate(KERNEL_NAMES + ["other"])},
