@@ -76,10 +76,18 @@ ROWS8N7 = Geometry(70, 45, 13, 0.9, 1.1, 1.0, 150, 61, 0.8, 0.85, sad=300.0, sdd
                    angles=_RAGGED_ANGLES)
 
 
+# detector columns three voxels wide with rows a third of a slice: an
+# 8-row plan whose 64-column blocks span up to ~140 trans positions on their
+# far planes, beyond the 128-element staging rows, so those blocks take the
+# staged kernel's direct path (global loads of the level stacks)
+COARSE_COLS = Geometry(60, 50, 10, 1.0, 1.0, 1.0, 70, 40, 3.0, 0.3, sad=300.0, sdd=450.0,
+                       n_views=5)
+
+
 @pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE, ROWS16, ROWS16_MANY, ROWS8N4, ROWS8N6,
-                               ROWS8N7],
+                               ROWS8N7, COARSE_COLS],
                          ids=["tiny", "ragged", "degenerate", "rows16", "rows16_many", "rows8n4",
-                              "rows8n6", "rows8n7"])
+                              "rows8n6", "rows8n7", "coarse_cols"])
 def test_project_parity(g):
     dev = _dev()
     f = inputs.random_volume(g, 1)
@@ -92,8 +100,8 @@ def test_project_parity(g):
 # ROWS16's footprints take both LDS paths of the backprojector (the
 # four-wave quarter scan and the column-per-lane scan) and include blocks
 # whose footprint lies off the detector for some views
-@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE, ROWS16],
-                         ids=["tiny", "ragged", "degenerate", "rows16"])
+@pytest.mark.parametrize("g", [TINY, RAGGED, DEGENERATE, ROWS16, COARSE_COLS],
+                         ids=["tiny", "ragged", "degenerate", "rows16", "coarse_cols"])
 def test_backproject_parity(g):
     dev = _dev()
     y = inputs.random_sino(g, 2)
