@@ -239,6 +239,34 @@ def test_reconstruct_two_grid_parity(momentum, levels):
     assert rel(host(got), want) <= 1e-3
 
 
+# deeper schedules than the two-grid workloads: three and four grids (odd
+# volume sizes, whose coarse grids round up), with and without detector
+# binning, a 2-level framelet and the positivity projection off
+@pytest.mark.parametrize("vol,iters,levels,binning,positivity", [
+    ((64, 56, 24), [2, 2, 2], 2, True, True),
+    ((61, 50, 19), [1, 2, 2], 1, True, True),
+    ((48, 40, 16), [1, 1, 1, 2], 1, False, True),
+    ((48, 40, 16), [2, 3], 2, True, False),
+], ids=["3grid_l2", "3grid_odd", "4grid_nobin", "2grid_nopos"])
+def test_reconstruct_multigrid_parity(vol, iters, levels, binning, positivity):
+    dev = _dev()
+    nx, ny, nz = vol
+    g = Geometry(nx, ny, nz, 1.5, 1.5, 1.5, 128, 64, 1.6, 1.6, n_views=24)
+    ells = inputs.tiny_phantom(13)
+    y = inputs.poisson_log(inputs.analytic_projection(g, ells), 1e5, 14)
+    announce("reconstruct %s iters %s levels %d binning %s positivity %s"
+             % (vol, iters, levels, binning, positivity))
+    got, rep = tfcb.reconstruct(g, t32(y, dev), 5e-4, iters, framelet_levels=levels,
+                                bin_detector=binning, positivity=positivity)
+    want, wrep = oracle.reconstruct(g, y, 5e-4, iters, framelet_levels=levels,
+                                    bin_detector=binning, positivity=positivity)
+    e = rel(host(got), want)
+    print("multigrid %s %s: rel L2 vs FP64 oracle %.2e" % (vol, iters, e), flush=True)
+    assert rep["iters_done"][:len(iters)] == iters
+    assert rep["resid2_last"] == pytest.approx(wrep["resid2_last"], rel=1e-2)
+    assert e <= 1e-3
+
+
 def test_reconstruct_deterministic():
     dev = _dev()
     cfg = inputs.config("tiny")
