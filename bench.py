@@ -262,6 +262,51 @@ def kernel_fractions(g, avg_ms, samples, copy_Bps=None):
     return out
 
 
+def with_transfers(g, yd, cfg, dev, reps: int = 3) -> dict:
+    """Seconds per reconstruction when the projections start in pinned host
+    memory and the volume ends there: the host-to-device copy, the
+    reconstruction (FP32 storage) and the device-to-host copy, on one
+    stream, median of reps after one untimed run."""
+    import torch
+    from paper_1008_2042_amd import tfcb
+    h_proj = torch.empty(yd.shape, dtype=torch.float32, pin_memory=True)
+    h_proj.copy_(yd.cpu())
+    h_vol = torch.empty(g.vol_shape, dtype=torch.float32, pin_memory=True)
+    d_proj = torch.empty_like(yd)
+    d_vol = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)
+    opts = tfcb.options(cfg["lam"], cfg["iters"], cfg["cgls_steps"], cfg["framelet_levels"])
+    ws = torch.empty(tfcb.workspace_size(g, opts), dtype=torch.uint8, device=dev)
+
+    def once():
+        d_proj.copy_(h_proj, non_blocking=True)
+        tfcb.reconstruct(g, d_proj, cfg["lam"], cfg["iters"], cfg["cgls_steps"],
+                         cfg["framelet_levels"], out=d_vol, ws=ws)
+        h_vol.copy_(d_vol, non_blocking=True)
+        torch.cuda.synchronize()
+
+    once()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        once()
+        ts.append(time.perf_counter() - t0)
+    # the two copies alone, event-timed
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    d_proj.copy_(h_proj, non_blocking=True)
+    e[1].record()
+    h_vol.copy_(d_vol, non_blocking=True)
+    e[2].record()
+    torch.cuda.synchronize()
+    out = {"s_per_recon": round(float(sorted(ts)[len(ts) // 2]), 4),
+           "h2d_projections_ms": round(e[0].elapsed_time(e[1]), 3),
+           "d2h_volume_ms": round(e[1].elapsed_time(e[2]), 3),
+           "note": "projections from pinned host memory, volume back to pinned host memory, "
+                   "median of %d" % reps}
+    del ws, d_proj, d_vol
+    return out
+
+
 def oracle_samples_error(vol):
     """Relative L2 error of a paper-scale GPU volume against the FP64
     oracle's full-schedule reconstruction at its stored samples (three
@@ -413,6 +458,7 @@ def main():
     }
     if args.workload == "paper":
         line["config"]["rel_l2_vs_oracle_samples"] = oracle_samples_error(vol32)
+        line["config"]["with_host_transfers"] = with_transfers(g, yd, cfg, dev)
     if not args.no_f16:
         for name, code in (("f16_storage", tfcb.F16), ("bf16_storage", tfcb.BF16)):
             volh, dth, _ = run(code, args.steps, 1, False)
