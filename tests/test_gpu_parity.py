@@ -7,6 +7,7 @@ final FP32 volume 1e-3.
 """
 import math
 import sys
+import threading
 
 import numpy as np
 import pytest
@@ -276,6 +277,44 @@ def test_reconstruct_deterministic():
     a, _ = tfcb.reconstruct(g, y, cfg["lam"], [3])
     b, _ = tfcb.reconstruct(g, y, cfg["lam"], [3])
     assert torch.equal(a, b)
+
+
+def test_concurrent_calls_on_two_streams_match_alone():
+    """Calls are reentrant with distinct workspaces and streams: a TF and a
+    TV reconstruction run at once from two host threads on two streams
+    give bitwise the results each gives alone."""
+    dev = _dev()
+    cfg = inputs.config("tiny")
+    g1 = cfg["geom"]
+    y1 = t32(inputs.measured_data(cfg), dev)
+    g2 = Geometry(48, 40, 12, 1.5, 1.5, 1.5, 96, 48, 2.0, 2.0, n_views=20)
+    y2 = t32(inputs.analytic_projection(g2, inputs.tiny_phantom(7)), dev)
+    jobs = [lambda: tfcb.reconstruct(g1, y1, cfg["lam"], [6])[0],
+            lambda: tfcb.reconstruct(g2, y2, 5e-4, [2, 3], regulariser=1)[0]]
+    announce("two threads on two streams")
+    alone = [job().clone() for job in jobs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    results, errors = [None, None], []
+
+    def run(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                out = jobs[i]()
+                results[i] = out.clone()
+            streams[i].synchronize()
+        except Exception as e:  # reported after the join
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    torch.cuda.synchronize()
+    assert torch.equal(results[0], alone[0])
+    assert torch.equal(results[1], alone[1])
 
 
 # ------------------------------------------------------------- full size
