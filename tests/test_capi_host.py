@@ -2,9 +2,11 @@
 symbol include/tfcb.h declares, sizes workspaces, and rejects bad arguments
 before touching the device."""
 import ctypes
+import dataclasses
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1008_2042_amd import inputs, tfcb
@@ -178,3 +180,47 @@ def test_tv_options_and_rof_arguments_checked():
                         ctypes.byref(nul)) == tfcb.EINVAL
     assert lib.tfcb_rof(*args, 256, 512, 256, n.value - 1, None, ctypes.byref(nul)) \
         == tfcb.ENOMEM
+
+
+def test_geometry_size_limits_and_angles():
+    """Sizes past the library's index limits and non-finite angles are
+    refused before any work, with a message naming the limit."""
+    lib = _lib()
+    n = ctypes.c_size_t(0)
+    base = inputs.config("tiny")["geom"]
+    cases = [
+        (dict(nz=70000), tfcb.EUNSUPPORTED, "65535"),
+        (dict(nv=20000), tfcb.EUNSUPPORTED, "detector"),
+        # 2^31 voxels
+        (dict(nx=2048, ny=2048, nz=600, dx=0.01, dy=0.01, dz=0.01), tfcb.EUNSUPPORTED, "2^31"),
+        # the padded copy alone exceeds 2^31 elements: (nz + 12) * 4096 * 4100
+        (dict(nx=4096, ny=4096, nz=120, dx=0.01, dy=0.01, dz=0.01), tfcb.EUNSUPPORTED,
+         "padded"),
+    ]
+    for kw, want, word in cases:
+        g = tfcb.geometry(dataclasses.replace(base, **kw))
+        st = lib.tfcb_operator_workspace_size(ctypes.byref(g), 0, ctypes.byref(n))
+        assert st == want, (kw, st)
+        assert word in lib.tfcb_last_error().decode(), (kw, lib.tfcb_last_error())
+    ang = np.linspace(0.0, 6.0, base.n_views)
+    ang[3] = float("inf")
+    g = tfcb.geometry(dataclasses.replace(base, angles=ang))
+    assert lib.tfcb_operator_workspace_size(ctypes.byref(g), 0, ctypes.byref(n)) == tfcb.EINVAL
+    assert "angle 3" in lib.tfcb_last_error().decode()
+
+
+def test_fdk_arguments_checked():
+    """FDK assumes the circular orbit's uniform angles and a row that fits its
+    filter's LDS staging; both are checked on the host before any work."""
+    lib = _lib()
+    n = ctypes.c_size_t(0)
+    base = inputs.config("tiny")["geom"]
+    g = tfcb.geometry(base)
+    assert lib.tfcb_fdk_workspace_size(ctypes.byref(g), ctypes.byref(n)) == 0
+    assert n.value >= base.n_views * base.nv * base.nu * 4
+    g = tfcb.geometry(dataclasses.replace(base, angles=np.linspace(0.0, 6.0, base.n_views)))
+    assert lib.tfcb_fdk(ctypes.byref(g), 0, 256, 256, 256, 1 << 30, None) == tfcb.EUNSUPPORTED
+    assert "angles" in lib.tfcb_last_error().decode()
+    g = tfcb.geometry(dataclasses.replace(base, nu=9000, du=0.01))
+    assert lib.tfcb_fdk(ctypes.byref(g), 0, 256, 256, 256, 1 << 30, None) == tfcb.EUNSUPPORTED
+    assert "8192" in lib.tfcb_last_error().decode()
