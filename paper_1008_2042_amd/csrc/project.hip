@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_project(GeomDev g, const ViewInfo* __re
 constexpr int kStageF4 = 32;    // 4-element vectors per staged level row
 constexpr int kStageRows = 24;  // level rows per staged plane
 constexpr int kStageRegs = (kStageRows * kStageF4 + 255) / 256;
-constexpr int kStageBoxes = 512;  // planes whose boxes a block tabulates in LDS (8 KB)
+constexpr int kStageBoxes = 512;  // planes whose boxes a block tabulates in LDS (8 KB; 4 KB packed)
 
 // Four consecutive stored elements, loaded as they are stored (a float4, or
 // 8 bytes of FP16/BF16) and widened to FP32 only when written to LDS, so
