@@ -513,6 +513,11 @@ def main():
     if args.serving > 0 and args.workload == "paper":
         from paper_1008_2042_amd import serve
         line["config"]["serving"] = serve.serving_benchmark(n=args.serving, device=dev)
+        # the same mix with plain FP32 storage, for the latency against FP32
+        sf = serve.serving_benchmark(n=args.serving, device=dev, storage=tfcb.F32)
+        line["config"]["serving_f32_storage"] = {
+            k: sf[k] for k in ("capacity_recons_per_min", "recons_per_min", "makespan_s",
+                               "p50", "p95", "p99", "max_slots", "storage")}
     if args.large:
         # the large single reconstruction, FP32 and FP16 storage, in the same run
         lcfg = inputs.config("large")
