@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInf
                                                      double* __restrict__ partials) {
   __shared__ double red[4];
   __shared__ float2 pre[kPrefTile];
-  __shared__ float2 qtot[3][kChunks * 64];  // quarter totals of the four-wave scan
+  // group totals of the four-wave scan: 3 x 64 (quarters) or 7 x 32 (halves)
+  __shared__ float2 qtot[256];
   __shared__ float cbox[2][2][8];  // projected corner columns / rows, two views
   const float rc = 0.5f * (float)(g.nv - 1);
 
@@ -217,24 +218,50 @@ __global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInf
                           W * Hq <= kPrefTile;
     const int Hp = quarters ? Hq : ((H + 1) | 1);
     const bool staged = quarters || (W > 0 && H > 0 && W * Hp <= kPrefTile);
-    const int q0 = kQuarterRows * wv;
-    const bool qrows = quarters && q0 < H;  // this wave has rows to scan
-    const float wq = (float)(r0 + q0 - rm);  // row offset of the quarter's first row
+    // Footprints at most 32 columns wide are scanned in halves: each wave
+    // takes two groups of 8 rows, one per half-wave (lanes 0-31 rows
+    // [16 w, 16 w + 8), lanes 32-63 rows [16 w + 8, 16 w + 16)), so a lane
+    // sums 8 rows instead of 16.  The scalar row pointer then steps without
+    // the clamp at r1 (the upper half reads 8 rows below it): rows past the
+    // footprint land, as before, in groups no later group reads and in the
+    // column's padding.  An active group starts above row H, so the rows
+    // read reach r1 + 7 at most; those must lie in the buffer, which holds
+    // for every view but the bottom rows of the last one (such a view takes
+    // the quarter scan).
+    const bool halves = quarters && W <= 32 && r1 + 7 < (g.n_views - view) * g.nv;
+    const int hsel = halves ? (lane >> 5) : 0;
+    const int grp = halves ? 2 * wv + hsel : wv;  // this lane's row group
+    const int cl = halves ? (lane & 31) : lane;   // this lane's footprint column
+    const int q0 = (halves ? 8 : kQuarterRows) * grp;
+    const bool qrows = quarters && q0 < H;  // this lane's group has rows to scan
+    const float wq = (float)(r0 + q0 - rm);  // row offset of the group's first row
     float qv[kChunks][kQuarterRows];
     if (qrows) {
+      if (halves) {
+        // a scalar row pointer stepped down 8 rows from row 16 w, a 32-bit
+        // offset per lane (its column, and 8 rows for the upper half)
+        const uint32_t cb = (uint32_t)((min(cl, W - 1) + hsel * 8 * g.nu) * (int)sizeof(T));
+        const T* __restrict__ rp = rview + (size_t)(r0 + kQuarterRows * wv) * g.nu + c0;
 #pragma unroll
-      for (int h = 0; h < kChunks; ++h) {
-        if (h == 1 && W <= 64) break;
-        // a scalar row pointer stepped down the rows, a 32-bit column offset per lane
-        const uint32_t cb = (uint32_t)(min(lane + 64 * h, W - 1) * sizeof(T));
-        const T* __restrict__ rp = rview + (size_t)(r0 + q0) * g.nu + c0;
-        int row = r0 + q0;
+        for (int u = 0; u < 8; ++u) {
+          qv[0][u] = ld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(rp) + cb));
+          rp += g.nu;
+        }
+      } else {
 #pragma unroll
-        for (int u = 0; u < kQuarterRows; ++u) {
-          qv[h][u] = ld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(rp) + cb));
-          const bool step = row < r1;
-          rp += step ? g.nu : 0;
-          row += step ? 1 : 0;
+        for (int h = 0; h < kChunks; ++h) {
+          if (h == 1 && W <= 64) break;
+          // a scalar row pointer stepped down the rows, a 32-bit column offset per lane
+          const uint32_t cb = (uint32_t)(min(lane + 64 * h, W - 1) * sizeof(T));
+          const T* __restrict__ rp = rview + (size_t)(r0 + q0) * g.nu + c0;
+          int row = r0 + q0;
+#pragma unroll
+          for (int u = 0; u < kQuarterRows; ++u) {
+            qv[h][u] = ld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(rp) + cb));
+            const bool step = row < r1;
+            rp += step ? g.nu : 0;
+            row += step ? 1 : 0;
+          }
         }
       }
     }
@@ -281,7 +308,18 @@ __global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInf
         pf1[q] = reinterpret_cast<const int4*>(cview + c)[1];
       }
     }
-    if (qrows && wv < 3) {
+    if (halves) {
+      // sum (wq + u) v = wq sum v + sum u v
+      if (qrows && grp < 7 && cl < W) {
+        float s0 = 0.f, su = 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          s0 += qv[0][u];
+          su = fmaf((float)u, qv[0][u], su);
+        }
+        qtot[grp * 32 + cl] = make_float2(s0, fmaf(wq, s0, su));
+      }
+    } else if (qrows && wv < 3) {
 #pragma unroll
       for (int h = 0; h < kChunks; ++h) {
         if (h == 1 && W <= 64) break;
@@ -293,12 +331,30 @@ __global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInf
           su = fmaf((float)u, qv[h][u], su);
         }
         const int cc = lane + 64 * h;
-        if (cc < W) qtot[wv][cc] = make_float2(s0, fmaf(wq, s0, su));
+        if (cc < W) qtot[wv * 64 + cc] = make_float2(s0, fmaf(wq, s0, su));
       }
     }
     __syncthreads();  // B1
     if (view + 1 < g.n_views) corners(view + 1, cb ^ 1);
-    if (qrows) {
+    if (qrows && halves) {
+      if (cl < W) {
+        float s0 = 0.f, s1 = 0.f, w = wq;
+        for (int k = 0; k < grp; ++k) {
+          const float2 qt = qtot[k * 32 + cl];
+          s0 += qt.x;
+          s1 += qt.y;
+        }
+        float2* __restrict__ dst = pre + cl * Hp + q0 + 1;
+        if (grp == 0) dst[-1] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          s0 += qv[0][u];
+          s1 = fmaf(w, qv[0][u], s1);
+          w += 1.f;
+          dst[u] = make_float2(s0, s1);
+        }
+      }
+    } else if (qrows) {
 #pragma unroll
       for (int h = 0; h < kChunks; ++h) {
         if (h == 1 && W <= 64) break;
@@ -306,7 +362,7 @@ __global__ __launch_bounds__(256, 4) void k_backproject(GeomDev g, const ViewInf
         if (cc < W) {
           float s0 = 0.f, s1 = 0.f, w = wq;
           for (int k = 0; k < wv; ++k) {
-            const float2 qt = qtot[k][cc];
+            const float2 qt = qtot[k * 64 + cc];
             s0 += qt.x;
             s1 += qt.y;
           }
